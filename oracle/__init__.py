@@ -1,0 +1,27 @@
+"""Plain CPU FP64 oracle for the CountGauss transform T.X = G.(S.X).
+
+TEST INFRASTRUCTURE ONLY.  This package is imported by ``tests/``, by
+``__graft_entry__.smoke()`` and by the ``cpu_baseline`` leg of ``bench.py``.
+The product path (the HIP library and its Python binding) never imports,
+calls, links or executes anything here, and this package imports nothing
+from the product path.  The two share no code: the random-number and hash
+specification is written out independently on each side.
+
+Every function is written for clarity, not speed: FP64 throughout, whole
+matrices materialised where that makes the definition visible.
+
+Parity status per function (what pins it against something other than
+itself is listed in tests/test_oracle_*.py):
+  philox4x32_10      pinned: published known-answer vectors (Salmon et al.)
+  hash_rows          pinned: structure of S (Section 2), uniformity and
+                     collision statistics, Lemma lb worked identity (Sec. 7)
+  gaussian_block     pinned: Box-Muller radius/angle identities, KS vs the
+                     normal CDF, bound, nesting
+  sketch_*           pinned: brute-force dense product, injective special
+                     case, closed-form E||M-C||_F^2, covariance over seeds,
+                     conditional whitening KS (Theorem 1 setting)
+  adjoint_*          pinned: adjoint identity and central differences
+  quantise_bf16/fp8  pinned: torch CPU dtype conversions (library routines)
+  emulate_reduced    parity unpinned (a diagnostic; no external reference)
+"""
+from .countgauss import *  # noqa: F401,F403
