@@ -1,0 +1,247 @@
+#!/usr/bin/env python
+"""Benchmark of the CountGauss transform T.X = G.(S.X) on one MI355X.
+
+Default workload: CSR X with n = 2^24 rows, d = 32 columns, density 5%
+(about 26.8M stored entries, values |N(0,1)|, FP32), m = 64, B = 65536 --
+the FP32-at-scale workload.  One step is one whole T.X call (zero S X,
+atomic S X, split MFMA contraction with in-register G, fixed-order
+reduction) on inputs already resident in HBM.
+
+Prints ONE JSON line on stdout (everything else goes to stderr):
+  value        nnz(X) / wall time per step (nnz/s)
+  roofline     the S X kernel (the dominant one): algorithmic bytes per
+               launch / its average duration from HIP events recorded by the
+               library on the launch stream, against the 8 TB/s HBM peak
+  cpu_baseline the FP64 oracle on the host cores, same workload
+  ladder       the G.(S X) precision ladder on the dense spiky workload
+               (n = 2^22, d = 64, m = 64, B = 262144): time per step and
+               error against the FP64 oracle for FP32, BF16 and FP8 inputs
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_FP32_TFLOPS = 157.3
+METRIC = "T·X nnz/sec and % HBM roofline at 1 GPU; fused BF16/FP8 vs FP32 at stated error"
+COUNTERS = os.path.join(ROOT, "profiles", "sx_csr_atomic_counters.json")
+SX_SOURCE = os.path.join(ROOT, "paper_1606_05732_amd", "csrc", "cg_sx_atomic.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """hipEvent_t handles through the HIP runtime torch already loaded."""
+
+    def __init__(self):
+        import torch  # noqa: F401  (loads the runtime)
+        self.rt = None
+        for name in ("libamdhip64.so.7", "libamdhip64.so"):
+            try:
+                self.rt = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+        if self.rt is None:
+            raise RuntimeError("HIP runtime not found")
+        self.rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                ctypes.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self, k):
+        out = []
+        for _ in range(k):
+            h = ctypes.c_void_p()
+            if self.rt.hipEventCreate(ctypes.byref(h)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            out.append(h.value)
+        return out
+
+    def ms(self, a, b):
+        f = ctypes.c_float()
+        if self.rt.hipEventElapsedTime(ctypes.byref(f), ctypes.c_void_p(a), ctypes.c_void_p(b)) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return f.value
+
+    def destroy(self, hs):
+        for h in hs:
+            self.rt.hipEventDestroy(ctypes.c_void_p(h))
+
+
+def timed_steps(plan, steps, warmup, ev):
+    """Run warmup + timed steps; returns wall ms/step and per-stage event
+    times (ms, averaged over the timed steps)."""
+    import torch
+    for _ in range(warmup):
+        plan.run()
+    sets = [ev.create(5) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        plan.set_stage_events(sets[i])
+        plan.run()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    plan.set_stage_events(None)
+    names = ["zero", "sx", "gsx", "reduce"]
+    stage = {k: 0.0 for k in names}
+    total = 0.0
+    for s in sets:
+        for j, k in enumerate(names):
+            stage[k] += ev.ms(s[j], s[j + 1]) / steps
+        total += ev.ms(s[0], s[4]) / steps
+    for s in sets:
+        ev.destroy(s)
+    return wall, stage, total
+
+
+def counters_traffic(kernel_launches_bytes):
+    """HBM bytes per launch of the S X kernel from committed rocprofv3
+    counter summaries, if they were taken on the current kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as f:
+        c = json.load(f)
+    src = hashlib.sha256(open(SX_SOURCE, "rb").read()).hexdigest()
+    if c.get("kernel_source_sha256") != src:
+        return None
+    return c.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(w):
+    import numpy as np  # noqa: F401
+    import oracle as O
+    c = w.csr
+    runs = []
+    cpu = []
+    for _ in range(2):
+        t0, c0 = time.perf_counter(), os.times()
+        O.sketch_csr(c.row_ptr, c.col_idx, c.vals, c.n, c.d, w.m, w.B, w.seed)
+        c1 = os.times()
+        runs.append(time.perf_counter() - t0)
+        cpu.append((c1.user - c0.user) + (c1.system - c0.system))
+    t = sorted(runs)[0]
+    cores = max(1, round(sum(cpu) / sum(runs)))
+    return {"value": c.nnz / t, "unit": "nnz/s", "cores": cores, "kind": "oracle",
+            "sample": f"whole workload ({c.nnz} stored entries), best of 2 runs, "
+                      f"{t:.2f} s per run, numpy FP64; host has {os.cpu_count()} logical CPUs"}
+
+
+def ladder(steps, warmup, ev):
+    import numpy as np  # noqa: F401
+    import torch
+
+    import oracle as O
+    import paper_1606_05732_amd as cg
+    from paper_1606_05732_amd import workloads as W
+    w = W.workload3()
+    log("ladder: oracle FP64 reference ...")
+    ref = O.sketch_dense(w.dense, w.m, w.B, w.seed)
+    X = torch.from_numpy(w.dense).to("cuda")
+    out = {"workload": w.name, "nnz": int(w.nnz)}
+    for prec in ("native", "bf16", "fp8"):
+        plan = cg.SketchPlan(X, w.m, w.B, w.seed, precision=prec)
+        wall, stage, total = timed_steps(plan, steps, warmup, ev)
+        err = O.rel_frobenius(plan.Y.cpu().numpy(), ref)
+        flops = 2.0 * w.m * w.B * w.d
+        out["fp32" if prec == "native" else prec] = {
+            "ms_per_step": round(wall, 4), "gsx_us": round(stage["gsx"] * 1e3, 2),
+            "sx_us": round(stage["sx"] * 1e3, 2),
+            "gsx_tflops": round(flops / (stage["gsx"] * 1e-3) / 1e12, 2),
+            "rel_fro_err_vs_fp64": float(f"{err:.3e}")}
+        log(f"ladder {prec}: {wall:.3f} ms/step, gsx {stage['gsx']*1e3:.1f} us, err {err:.2e}")
+        del plan
+    del X
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--algo", default="atomic", choices=["atomic", "sorted"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ladder", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the transform shards by rows with one m x d all-reduce; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1606_05732_amd as cg
+    from paper_1606_05732_amd import workloads as W
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    ev = HipEvents()
+    log("generating workload ...")
+    w = W.workload2()
+    c = w.csr
+    X = cg.CsrMatrix(torch.from_numpy(c.row_ptr).cuda(), torch.from_numpy(c.col_idx).cuda(),
+                     torch.from_numpy(c.vals).cuda(), c.n, c.d)
+    plan = cg.SketchPlan(X, w.m, w.B, w.seed, algo=args.algo)
+    log(f"workload {w.name}: nnz {c.nnz}, workspace {plan.workspace_bytes/2**20:.1f} MiB")
+    wall, stage, total = timed_steps(plan, args.steps, args.warmup, ev)
+    nnz = c.nnz
+    sx_bytes = 8 * nnz + 4 * (c.n + 1) + 4 * w.B * c.d
+    sx_s = stage["sx"] * 1e-3
+    achieved = sx_bytes / sx_s / 1e9
+    gsx_flops = 2.0 * w.m * w.B * c.d
+    log(f"wall {wall:.4f} ms/step; events: zero {stage['zero']*1e3:.1f} us, "
+        f"sx {stage['sx']*1e3:.1f} us, gsx {stage['gsx']*1e3:.1f} us, "
+        f"reduce {stage['reduce']*1e3:.1f} us, total {total*1e3:.1f} us")
+    result = {
+        "metric": METRIC,
+        "value": nnz / (wall * 1e-3),
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": c.n, "d": c.d, "density": 0.05, "nnz": nnz,
+                   "m": w.m, "B": w.B, "values": "|N(0,1)| float32", "sx_algo": args.algo,
+                   "precision": "fp32", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": f"sx_csr_{args.algo}",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counters_traffic(sx_bytes),
+                     "algorithmic_bytes_per_launch": sx_bytes,
+                     "avg_launch_us": round(stage["sx"] * 1e3, 2)},
+        "stages_us": {k: round(v * 1e3, 2) for k, v in stage.items()},
+        "gsx": {"avg_launch_us": round(stage["gsx"] * 1e3, 2),
+                "tflops": round(gsx_flops / (stage["gsx"] * 1e-3) / 1e12, 3),
+                "frac_fp32_mfma_peak": round(gsx_flops / (stage["gsx"] * 1e-3) / 1e12
+                                             / MFMA_FP32_TFLOPS, 4),
+                "normals_per_launch": w.m * w.B},
+    }
+    del plan, X
+    torch.cuda.empty_cache()
+    if not args.no_ladder:
+        result["ladder"] = ladder(max(5, args.steps // 2), 2, ev)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,252 @@
+/*
+ * countgauss.h -- C ABI of libcountgauss.so, the MI355X (gfx950) CountGauss
+ * transform.
+ *
+ * The transform (Kapralov, Potluru, Woodruff, "How to Fake Multiply by a
+ * Gaussian Matrix", Section 1.1 and Section 2): an n x d input X (n >> d,
+ * dense or sparse with nnz(X) stored entries) is mapped to the m x d result
+ *
+ *     Y = T X = G (S X),
+ *
+ * where S is a B x n CountSketch (column r has its one nonzero, sigma(r) in
+ * {+1,-1}, at row h(r)) and G is an m x B matrix of i.i.d. unit-variance
+ * Gaussians (Theorem 1; no 1/sqrt(m) scaling).  S X costs O(nnz(X)) and
+ * G (S X) is a dense m x B by B x d product (Section 1.1).  T is fixed by
+ * (m, B, seed): the seed is the whole state, which is how the paper shares
+ * the transform between servers (Section 4, "Distributed Environments").
+ *
+ * Random source (the paper names none): Philox4x32-10, key = the 64-bit
+ * seed; row hash from counter (r>>2 as two words, 0, 0), word r&3:
+ * sigma = bit 31 ? -1 : +1, h = ((w & 0x7fffffff) * B) >> 31; G[i][b] is
+ * Box-Muller of the words of counter (b, i>>2, 1, 0), entry i&3, with
+ * u = ((w >> 9) + 1/2) 2^-23.  cg_debug_* expose these for testing.
+ *
+ * Conventions for every call:
+ *  - Pointers named as device pointers are device memory owned by the
+ *    caller; the library never allocates, frees or keeps them.  Host
+ *    pointers (opts, the batched table) are read during the call only,
+ *    except where stated.
+ *  - Matrices are row-major.  Indices are int32 (nnz < 2^31).
+ *  - Work is queued on opts->stream (a hipStream_t; NULL = the default
+ *    stream) and the call returns without waiting for it; results are
+ *    ready when the stream has passed this call.  Outputs are overwritten.
+ *  - Arguments are validated before anything is queued; on an error
+ *    nothing is queued and cg_last_error() holds a message (per thread).
+ *  - Scratch memory comes from opts->workspace (device), at least
+ *    cg_workspace_bytes() bytes, 256-byte aligned; its contents on entry
+ *    do not matter and are garbage afterwards.  Two calls in flight at the
+ *    same time must not share a workspace.
+ *  - Values are not checked for finiteness: a NaN in row r reaches bucket
+ *    h(r) of S X and then every entry of its column of Y.
+ *  - Column indices outside [0, d) and row_ptr entries outside [0, nnz]
+ *    are skipped / clamped on the device (no fault), giving an unspecified
+ *    result; row_ptr must be nondecreasing for a defined result.
+ */
+#ifndef COUNTGAUSS_H
+#define COUNTGAUSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define CG_OK 0
+#define CG_EINVAL 1         /* bad size, null pointer, unknown enum        */
+#define CG_ENOSPACE 2       /* workspace missing or smaller than required  */
+#define CG_EUNSUPPORTED 3   /* valid but outside this build (e.g. d > 1024) */
+#define CG_EHIP 4           /* a HIP runtime call failed (message kept)    */
+
+/* ---- element type of X / Y / dY / dX / S X ---------------------------- */
+#define CG_DTYPE_F32 0
+#define CG_DTYPE_F64 1
+
+/* ---- input precision of the G (S X) contraction ----------------------- *
+ * S X is always accumulated in the data type (FP32 for F32 data, FP64 for
+ * F64 data).  The contraction's inputs G and S X may be rounded to:       */
+#define CG_PREC_NATIVE 0    /* the data type itself (FP32 or FP64)          */
+#define CG_PREC_BF16 1      /* bfloat16, round to nearest even; F32 data    */
+#define CG_PREC_FP8 2       /* OCP FP8 E4M3 (max 448), round to nearest
+                               even, one power-of-two scale per 128-wide
+                               block of B for S X and the constant 2^-6 for
+                               G (|G| < 5.77); F32 data                     */
+/* All precisions accumulate the contraction in the data type (FP32 for
+ * BF16/FP8) and reduce the split over B in a fixed order.                */
+
+/* ---- algorithm for S X ------------------------------------------------- */
+#define CG_SX_AUTO 0        /* library's choice (the atomic path)           */
+#define CG_SX_ATOMIC 1      /* one device-scope atomic add per stored entry;
+                               summation order within a bucket varies from
+                               run to run in FP32                           */
+#define CG_SX_SORTED 2      /* rows grouped by bucket (counting sort), each
+                               bucket summed in increasing row order:
+                               bitwise reproducible                         */
+
+/* ---- workspace kinds --------------------------------------------------- */
+#define CG_KIND_CSR 0
+#define CG_KIND_DENSE 1
+#define CG_KIND_ADJOINT 2
+#define CG_KIND_ADJOINT_CSR 3
+
+typedef struct cg_opts {
+  uint32_t struct_size;     /* sizeof(cg_opts)                             */
+  int32_t precision;        /* CG_PREC_*                                   */
+  int32_t sx_algo;          /* CG_SX_*                                     */
+  int32_t kc;               /* columns of G per wavefront in the contraction,
+                               a multiple of 16; 0 = library's choice      */
+  void* stream;             /* hipStream_t, NULL = default stream          */
+  void* workspace;          /* device scratch                              */
+  size_t workspace_bytes;   /* its size                                    */
+  int64_t row_offset;       /* global index of local row 0: hashing uses
+                               row_offset + r, so row chunks or shards of
+                               one X sketch consistently and their Y add up
+                               (Section 4, distributed environments)       */
+  void* sx_out;             /* optional device B x d buffer (data type): if
+                               non-NULL S X is accumulated there and left
+                               for the caller; otherwise in the workspace  */
+  void* const* stage_events;/* optional host array of CG_STAGE_EVENTS
+                               hipEvent_t created by the caller; forward
+                               calls record them on the stream at the stage
+                               boundaries (see below); NULL = none          */
+} cg_opts;
+
+/* Forward stage boundaries recorded into cg_opts.stage_events:
+ *   [0] before any work            [1] after S X is zeroed (atomic path)
+ *   [2] after S X is complete      [3] after the split contraction
+ *   [4] after the fixed-order reduction (Y complete)                      */
+#define CG_STAGE_EVENTS 5
+
+/* Fill *opts with defaults (native precision, automatic S X algorithm,
+ * default stream, no workspace, row_offset 0). */
+void cg_opts_init(cg_opts* opts);
+
+/* Library version, e.g. 100 for 0.1.0. */
+int cg_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* cg_status_string(int status);
+
+/* Copy the calling thread's last error message into buf (NUL-terminated,
+ * truncated to len).  Returns the full message length. */
+size_t cg_last_error(char* buf, size_t len);
+
+/* Bytes of workspace the matching call needs for these sizes and options
+ * (nnz is ignored for dense kinds).  Returns CG_OK or CG_EINVAL. */
+int cg_workspace_bytes(int kind, int dtype, int64_t n, int64_t d, int64_t m,
+                       int64_t B, int64_t nnz, const cg_opts* opts,
+                       size_t* bytes);
+
+/*
+ * Y = G S X for CSR X (Section 1.1: S X in O(nnz(X)), then G (S X)).
+ *   row_ptr  device int32[n+1], row_ptr[0] = 0, row_ptr[n] = nnz
+ *   col_idx  device int32[nnz], column of each stored entry (in [0, d))
+ *   vals     device dtype[nnz]
+ *   Y        device dtype[m*d], overwritten
+ * 1 <= n, d <= 1024, 1 <= m, 1 <= B < 2^31, 0 <= nnz < 2^31.
+ * dtype F64 requires precision NATIVE.  Errors: CG_EINVAL, CG_ENOSPACE,
+ * CG_EUNSUPPORTED, CG_EHIP.
+ */
+int cg_sketch_csr(const int32_t* row_ptr, const int32_t* col_idx,
+                  const void* vals, int dtype, int64_t n, int64_t d,
+                  int64_t nnz, int64_t m, int64_t B, uint64_t seed, void* Y,
+                  const cg_opts* opts);
+
+/*
+ * Y = G S X for dense X (n x d, row stride ldx >= d elements).
+ * Same sizes, precisions and errors as cg_sketch_csr.
+ */
+int cg_sketch_dense(const void* X, int64_t ldx, int dtype, int64_t n,
+                    int64_t d, int64_t m, int64_t B, uint64_t seed, void* Y,
+                    const cg_opts* opts);
+
+/*
+ * Adjoint: dX = T^T dY = S^T (G^T dY), the gradient of <dY, T X> with
+ * respect to dense X (T = G S is linear, Section 1.1).  First
+ * Z = G^T dY (B x d, G regenerated), then dX[r][:] = sigma(r) Z[h(r)][:].
+ *   dY  device dtype[m*d];  dX device dtype, n rows of stride lddx >= d,
+ *   overwritten.  Precision must be NATIVE.
+ */
+int cg_sketch_adjoint(const void* dY, int dtype, int64_t n, int64_t d,
+                      int64_t m, int64_t B, uint64_t seed, void* dX,
+                      int64_t lddx, const cg_opts* opts);
+
+/*
+ * Adjoint for CSR X: gradient of <dY, T X> with respect to the stored
+ * values, dvals[k] = sigma(r) Z[h(r)][col_idx[k]] for the entry k of row r.
+ *   dvals device dtype[nnz], overwritten.
+ */
+int cg_sketch_adjoint_csr(const int32_t* row_ptr, const int32_t* col_idx,
+                          int64_t nnz, const void* dY, int dtype, int64_t n,
+                          int64_t d, int64_t m, int64_t B, uint64_t seed,
+                          void* dvals, const cg_opts* opts);
+
+/* ---- many independent instances in one persistent launch --------------- */
+typedef struct cg_instance {
+  /* set by the caller */
+  const int32_t* row_ptr;   /* device int32[n+1]                            */
+  const int32_t* col_idx;   /* device int32[nnz]                            */
+  const float* vals;        /* device float[nnz]                            */
+  float* Y;                 /* device float[m*d], overwritten               */
+  int64_t n, d, nnz, m, B;  /* as for cg_sketch_csr (FP32, native)          */
+  uint64_t seed;            /* this instance's transform                   */
+  int64_t row_offset;
+  /* set by cg_batched_plan; leave them as planned */
+  int64_t sx_off;           /* byte offset of this instance's S X           */
+  int64_t part_off;         /* byte offset of its split partials            */
+  int32_t sx_tiles;         /* S X work items (row chunks)                  */
+  int32_t gsx_tiles;        /* contraction work items (column blocks of G)  */
+  int32_t kc;               /* columns of G per contraction item            */
+  int32_t first_tile;       /* index of its first S X item in the queue     */
+} cg_instance;
+
+/*
+ * Plan a batch: validate every instance, choose its tile shapes (from the
+ * tuning table, see cg_set_tuning) and fill the planning fields of inst
+ * (host array, in/out).  *workspace_bytes receives the workspace the
+ * launch needs.  Errors: CG_EINVAL / CG_EUNSUPPORTED naming the instance.
+ */
+int cg_batched_plan(cg_instance* inst, int32_t count, const cg_opts* opts,
+                    size_t* workspace_bytes);
+
+/*
+ * One persistent launch computing every planned instance's Y (each with its
+ * own seed, m, B).  inst is the host table returned by cg_batched_plan; it
+ * is copied into the workspace on opts->stream and must stay valid and
+ * unchanged until the stream has passed this call.  FP32 data and native
+ * precision only.
+ */
+int cg_sketch_batched(const cg_instance* inst, int32_t count,
+                      const cg_opts* opts);
+
+/*
+ * Tuning table for the batched planner: for each d class (log2 d from 0
+ * to 10) the number of rows per S X item and G columns per contraction
+ * item.  NULL arguments restore the built-in table.  Host only.
+ */
+int cg_set_tuning(const int32_t* rows_per_item, const int32_t* kc_per_item,
+                  int32_t classes);
+
+/* ---- test access to the random source ---------------------------------- */
+
+/* out[4k..4k+3] = Philox4x32-10(counter ctr[4k..4k+3], key(seed)) for
+ * k < count.  ctr, out: device uint32 arrays.  stream: hipStream_t. */
+int cg_debug_philox(uint64_t seed, const uint32_t* ctr, int64_t count,
+                    uint32_t* out, void* stream);
+
+/* Bucket h and sign sigma (+1/-1) of global rows row0 .. row0+count-1.
+ * h: device uint32[count]; sigma: device int8[count]. */
+int cg_debug_hash(uint64_t seed, int64_t B, uint64_t row0, int64_t count,
+                  uint32_t* h, int8_t* sigma, void* stream);
+
+/* Columns b0 .. b0+nb-1 of G (m x B), written as device dtype[m*nb]
+ * row-major; FP32 values are what the FP32 contraction uses. */
+int cg_debug_gaussian(uint64_t seed, int64_t m, int64_t b0, int64_t nb,
+                      int dtype, void* G, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COUNTGAUSS_H */

@@ -1,0 +1,11 @@
+"""MI355X (gfx950) CountGauss transform T.X = G.(S.X).
+
+The transform of Kapralov, Potluru and Woodruff ("How to Fake Multiply by a
+Gaussian Matrix"): a seeded CountSketch S followed by an m x B Gaussian G,
+computed by hand-written HIP kernels in libcountgauss.so (C ABI in
+include/countgauss.h).  This package is a thin binding: torch provides
+device memory and streams.
+"""
+from .api import (CsrMatrix, CountGaussFn, countgauss, debug_gaussian, debug_hash,  # noqa: F401
+                  debug_philox, sketch, sketch_adjoint, sketch_adjoint_csr, SketchPlan)
+from ._lib import CountGaussError, LIB_PATH  # noqa: F401

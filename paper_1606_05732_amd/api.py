@@ -1,0 +1,304 @@
+"""Python face of libcountgauss.so: torch tensors in, torch tensors out.
+
+torch supplies device memory (inputs, outputs, workspace) and the current
+stream; every step of the transform runs in the library's HIP kernels.
+Nothing here computes any part of T.X.
+"""
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_PREC = {"native": L.CG_PREC_NATIVE, "fp32": L.CG_PREC_NATIVE, "fp64": L.CG_PREC_NATIVE,
+         "bf16": L.CG_PREC_BF16, "fp8": L.CG_PREC_FP8}
+_ALGO = {"auto": L.CG_SX_AUTO, "atomic": L.CG_SX_ATOMIC, "sorted": L.CG_SX_SORTED}
+
+
+@dataclass
+class CsrMatrix:
+    """CSR matrix on the GPU: row_ptr int32[n+1], col_idx int32[nnz],
+    vals float32/float64[nnz]."""
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    vals: torch.Tensor
+    n: int
+    d: int
+
+    @property
+    def nnz(self):
+        return int(self.col_idx.numel())
+
+    @classmethod
+    def from_torch(cls, t):
+        """From a torch.sparse_csr tensor (indices converted to int32)."""
+        return cls(t.crow_indices().to(torch.int32).contiguous(),
+                   t.col_indices().to(torch.int32).contiguous(),
+                   t.values().contiguous(), int(t.shape[0]), int(t.shape[1]))
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return L.CG_DTYPE_F32
+    if t.dtype == torch.float64:
+        return L.CG_DTYPE_F64
+    raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float64")
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("CountGauss runs on the GPU only: tensors must be on a CUDA/HIP device")
+
+
+def _workspace(nbytes, device):
+    """Device scratch of at least nbytes, 256-byte aligned (the buffer is
+    returned too, to keep it alive until the call's work is queued)."""
+    if nbytes == 0:
+        return None, None, 0
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    addr = buf.data_ptr()
+    pad = (-addr) % 256
+    return buf, addr + pad, nbytes
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _as_csr(X):
+    if isinstance(X, CsrMatrix):
+        return X
+    if isinstance(X, torch.Tensor) and X.layout == torch.sparse_csr:
+        return CsrMatrix.from_torch(X)
+    return None
+
+
+def sketch(X, m, B, seed, precision="native", algo="auto", row_offset=0, kc=0, sx_out=None):
+    """Y = T X = G (S X) (m x d) for dense X (n x d, unit column stride) or
+    CSR X (CsrMatrix or torch.sparse_csr).  precision: native (FP32/FP64),
+    bf16 or fp8 inputs to the G (S X) contraction.  algo: auto, atomic or
+    sorted (bitwise reproducible) S X.  sx_out: optional B x d tensor that
+    receives S X."""
+    lib = L.load()
+    prec = _PREC[precision]
+    sx_algo = _ALGO[algo]
+    csr = _as_csr(X)
+    if csr is not None:
+        vals = csr.vals
+        _require_cuda(csr.row_ptr, csr.col_idx, vals)
+        if csr.row_ptr.dtype != torch.int32 or csr.col_idx.dtype != torch.int32:
+            raise TypeError("CSR indices must be int32")
+        if csr.row_ptr.numel() != csr.n + 1:
+            raise ValueError("row_ptr must have n + 1 entries")
+        if vals.numel() != csr.col_idx.numel():
+            raise ValueError("vals and col_idx differ in length")
+        device, dt, n, d = vals.device, vals.dtype, csr.n, csr.d
+    else:
+        if not isinstance(X, torch.Tensor) or X.dim() != 2:
+            raise TypeError("X must be a 2-D dense tensor or a CSR matrix")
+        _require_cuda(X)
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        device, dt, (n, d) = X.device, X.dtype, X.shape
+    code = _dtype_code(torch.empty(0, dtype=dt))
+    Y = torch.empty((m, d), dtype=dt, device=device)
+    if sx_out is not None:
+        if sx_out.shape != (B, d) or sx_out.dtype != dt or not sx_out.is_contiguous():
+            raise ValueError("sx_out must be a contiguous B x d tensor of X's dtype")
+    opts = L.make_opts(prec, sx_algo, kc, _stream(device), None, 0, row_offset,
+                       _ptr(sx_out) if sx_out is not None else None)
+    nbytes = ctypes.c_size_t(0)
+    kind = L.CG_KIND_CSR if csr is not None else L.CG_KIND_DENSE
+    nnz = csr.nnz if csr is not None else 0
+    L.check(lib.cg_workspace_bytes(kind, code, n, d, m, B, nnz, ctypes.byref(opts),
+                                   ctypes.byref(nbytes)), "cg_workspace_bytes")
+    buf, addr, size = _workspace(nbytes.value, device)
+    opts.workspace, opts.workspace_bytes = addr, size
+    if csr is not None:
+        st = lib.cg_sketch_csr(_ptr(csr.row_ptr), _ptr(csr.col_idx), _ptr(csr.vals), code, n, d,
+                               nnz, m, B, ctypes.c_uint64(seed & (2 ** 64 - 1)), _ptr(Y),
+                               ctypes.byref(opts))
+        L.check(st, "cg_sketch_csr")
+    else:
+        st = lib.cg_sketch_dense(_ptr(X), X.stride(0), code, n, d, m, B,
+                                 ctypes.c_uint64(seed & (2 ** 64 - 1)), _ptr(Y), ctypes.byref(opts))
+        L.check(st, "cg_sketch_dense")
+    del buf
+    return Y
+
+
+def sketch_adjoint(dY, n, m, B, seed, row_offset=0, out=None):
+    """dX = T^T dY = S^T (G^T dY) (n x d) for a dense m x d upstream dY."""
+    lib = L.load()
+    _require_cuda(dY)
+    dY = dY.contiguous()
+    mm, d = dY.shape
+    if mm != m:
+        raise ValueError("dY must have m rows")
+    code = _dtype_code(dY)
+    dX = out if out is not None else torch.empty((n, d), dtype=dY.dtype, device=dY.device)
+    if dX.shape != (n, d) or dX.stride(1) != 1:
+        raise ValueError("out must be n x d with unit column stride")
+    opts = L.make_opts(L.CG_PREC_NATIVE, L.CG_SX_AUTO, 0, _stream(dY.device), None, 0, row_offset)
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.cg_workspace_bytes(L.CG_KIND_ADJOINT, code, n, d, m, B, 0, ctypes.byref(opts),
+                                   ctypes.byref(nbytes)), "cg_workspace_bytes")
+    buf, addr, size = _workspace(nbytes.value, dY.device)
+    opts.workspace, opts.workspace_bytes = addr, size
+    L.check(lib.cg_sketch_adjoint(_ptr(dY), code, n, d, m, B, ctypes.c_uint64(seed & (2 ** 64 - 1)),
+                                  _ptr(dX), dX.stride(0), ctypes.byref(opts)), "cg_sketch_adjoint")
+    del buf
+    return dX
+
+
+def sketch_adjoint_csr(X, dY, m, B, seed, row_offset=0):
+    """Gradient of <dY, T X> with respect to the stored values of CSR X."""
+    lib = L.load()
+    csr = _as_csr(X)
+    _require_cuda(dY, csr.row_ptr)
+    dY = dY.contiguous()
+    code = _dtype_code(dY)
+    dvals = torch.empty(csr.nnz, dtype=dY.dtype, device=dY.device)
+    opts = L.make_opts(L.CG_PREC_NATIVE, L.CG_SX_AUTO, 0, _stream(dY.device), None, 0, row_offset)
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.cg_workspace_bytes(L.CG_KIND_ADJOINT_CSR, code, csr.n, csr.d, m, B, csr.nnz,
+                                   ctypes.byref(opts), ctypes.byref(nbytes)), "cg_workspace_bytes")
+    buf, addr, size = _workspace(nbytes.value, dY.device)
+    opts.workspace, opts.workspace_bytes = addr, size
+    L.check(lib.cg_sketch_adjoint_csr(_ptr(csr.row_ptr), _ptr(csr.col_idx), csr.nnz, _ptr(dY),
+                                      code, csr.n, csr.d, m, B,
+                                      ctypes.c_uint64(seed & (2 ** 64 - 1)), _ptr(dvals),
+                                      ctypes.byref(opts)), "cg_sketch_adjoint_csr")
+    del buf
+    return dvals
+
+
+class CountGaussFn(torch.autograd.Function):
+    """Y = T X with the adjoint T^T dY as backward (dense X).  m, B, seed
+    and the options are not differentiable."""
+
+    @staticmethod
+    def forward(ctx, X, m, B, seed, row_offset=0):
+        ctx.shape = X.shape
+        ctx.m, ctx.B, ctx.seed, ctx.row_offset = m, B, seed, row_offset
+        return sketch(X, m, B, seed, row_offset=row_offset)
+
+    @staticmethod
+    def backward(ctx, dY):
+        dX = sketch_adjoint(dY, ctx.shape[0], ctx.m, ctx.B, ctx.seed, ctx.row_offset)
+        return dX, None, None, None, None
+
+
+def countgauss(X, m, B, seed, row_offset=0):
+    """Differentiable T X for dense X (autograd through CountGaussFn)."""
+    return CountGaussFn.apply(X, m, B, seed, row_offset)
+
+
+# ---- test access to the random source ----------------------------------
+def debug_philox(seed, ctr):
+    """Philox4x32-10 of each row of ctr (int32/uint32-valued tensor k x 4)."""
+    lib = L.load()
+    _require_cuda(ctr)
+    ctr = ctr.contiguous()
+    k = ctr.shape[0]
+    out = torch.empty((k, 4), dtype=torch.int32, device=ctr.device)
+    L.check(lib.cg_debug_philox(ctypes.c_uint64(seed & (2 ** 64 - 1)), _ptr(ctr), k, _ptr(out),
+                                _stream(ctr.device)), "cg_debug_philox")
+    return out
+
+
+def debug_hash(seed, B, row0, count, device="cuda"):
+    lib = L.load()
+    h = torch.empty(count, dtype=torch.int32, device=device)
+    s = torch.empty(count, dtype=torch.int8, device=device)
+    L.check(lib.cg_debug_hash(ctypes.c_uint64(seed & (2 ** 64 - 1)), B, ctypes.c_uint64(row0),
+                              count, _ptr(h), _ptr(s), _stream(torch.device(device))),
+            "cg_debug_hash")
+    return h, s
+
+
+def debug_gaussian(seed, m, b0, nb, dtype=torch.float32, device="cuda"):
+    lib = L.load()
+    G = torch.empty((m, nb), dtype=dtype, device=device)
+    code = _dtype_code(G)
+    L.check(lib.cg_debug_gaussian(ctypes.c_uint64(seed & (2 ** 64 - 1)), m, b0, nb, code, _ptr(G),
+                                  _stream(torch.device(device))), "cg_debug_gaussian")
+    return G
+
+
+class SketchPlan:
+    """A forward call with every buffer allocated up front: Y, optional S X
+    and the workspace.  run() only queues the library's kernels on the
+    current stream (no allocation), so it can sit in a timed loop.
+
+    stage_events: optional list of CG_STAGE_EVENTS raw hipEvent_t handles
+    (ints) that the library records at its stage boundaries."""
+
+    def __init__(self, X, m, B, seed, precision="native", algo="auto", row_offset=0, kc=0,
+                 keep_sx=False):
+        self.lib = L.load()
+        self.csr = _as_csr(X)
+        if self.csr is not None:
+            c = self.csr
+            _require_cuda(c.row_ptr, c.col_idx, c.vals)
+            if c.row_ptr.dtype != torch.int32 or c.col_idx.dtype != torch.int32:
+                raise TypeError("CSR indices must be int32")
+            self.device, dt, self.n, self.d = c.vals.device, c.vals.dtype, c.n, c.d
+            self.nnz = c.nnz
+        else:
+            _require_cuda(X)
+            if X.dim() != 2:
+                raise TypeError("X must be 2-D")
+            if X.stride(1) != 1:
+                X = X.contiguous()
+            self.device, dt, (self.n, self.d) = X.device, X.dtype, X.shape
+            self.nnz = self.n * self.d
+        self.X = X
+        self.m, self.B, self.seed = m, B, seed & (2 ** 64 - 1)
+        self.code = _dtype_code(torch.empty(0, dtype=dt))
+        self.Y = torch.empty((m, self.d), dtype=dt, device=self.device)
+        self.SX = torch.empty((B, self.d), dtype=dt, device=self.device) if keep_sx else None
+        self._events = None
+        self.opts = L.make_opts(_PREC[precision], _ALGO[algo], kc, None, None, 0, row_offset,
+                                _ptr(self.SX) if keep_sx else None)
+        nbytes = ctypes.c_size_t(0)
+        kind = L.CG_KIND_CSR if self.csr is not None else L.CG_KIND_DENSE
+        L.check(self.lib.cg_workspace_bytes(kind, self.code, self.n, self.d, m, B,
+                                            self.nnz if self.csr is not None else 0,
+                                            ctypes.byref(self.opts), ctypes.byref(nbytes)),
+                "cg_workspace_bytes")
+        self._ws, addr, size = _workspace(nbytes.value, self.device)
+        self.opts.workspace, self.opts.workspace_bytes = addr, size
+        self.workspace_bytes = size
+
+    def set_stage_events(self, handles):
+        if handles is None:
+            self._events = None
+            self.opts.stage_events = None
+            return
+        if len(handles) != L.CG_STAGE_EVENTS:
+            raise ValueError(f"need {L.CG_STAGE_EVENTS} event handles")
+        self._events = (ctypes.c_void_p * L.CG_STAGE_EVENTS)(*handles)
+        self.opts.stage_events = ctypes.cast(self._events, ctypes.c_void_p)
+
+    def run(self):
+        self.opts.stream = _stream(self.device)
+        seed = ctypes.c_uint64(self.seed)
+        if self.csr is not None:
+            c = self.csr
+            st = self.lib.cg_sketch_csr(_ptr(c.row_ptr), _ptr(c.col_idx), _ptr(c.vals), self.code,
+                                        self.n, self.d, self.nnz, self.m, self.B, seed,
+                                        _ptr(self.Y), ctypes.byref(self.opts))
+            L.check(st, "cg_sketch_csr")
+        else:
+            st = self.lib.cg_sketch_dense(_ptr(self.X), self.X.stride(0), self.code, self.n,
+                                          self.d, self.m, self.B, seed, _ptr(self.Y),
+                                          ctypes.byref(self.opts))
+            L.check(st, "cg_sketch_dense")
+        return self.Y

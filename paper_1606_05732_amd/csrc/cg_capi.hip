@@ -1,0 +1,360 @@
+// C ABI of libcountgauss.so: argument validation, workspace layout and
+// dispatch to the kernels.  Nothing here allocates device memory or waits
+// for the device; every error is reported before the first launch.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "countgauss.h"
+#include "cg_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(CG_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+struct Opts {
+  int precision = CG_PREC_NATIVE;
+  int sx_algo = CG_SX_AUTO;
+  int kc = 0;
+  hipStream_t stream = nullptr;
+  void* workspace = nullptr;
+  size_t workspace_bytes = 0;
+  int64_t row_offset = 0;
+  void* sx_out = nullptr;
+  void* const* events = nullptr;
+};
+
+int record(const Opts& o, int i) {
+  if (!o.events) return CG_OK;
+  hipError_t e = hipEventRecord((hipEvent_t)o.events[i], o.stream);
+  return e == hipSuccess ? CG_OK : hip_fail(e, "hipEventRecord(stage event)");
+}
+
+int read_opts(const cg_opts* o, Opts* out) {
+  *out = Opts();
+  if (!o) return CG_OK;
+  if (o->struct_size < sizeof(cg_opts))
+    return fail(CG_EINVAL, "cg_opts.struct_size %u < %zu", o->struct_size, sizeof(cg_opts));
+  out->precision = o->precision;
+  out->sx_algo = o->sx_algo;
+  out->kc = o->kc;
+  out->stream = (hipStream_t)o->stream;
+  out->workspace = o->workspace;
+  out->workspace_bytes = o->workspace_bytes;
+  out->row_offset = o->row_offset;
+  out->sx_out = o->sx_out;
+  out->events = o->stage_events;
+  if (out->precision < CG_PREC_NATIVE || out->precision > CG_PREC_FP8)
+    return fail(CG_EINVAL, "unknown precision %d", out->precision);
+  if (out->sx_algo < CG_SX_AUTO || out->sx_algo > CG_SX_SORTED)
+    return fail(CG_EINVAL, "unknown sx_algo %d", out->sx_algo);
+  if (out->kc < 0 || out->kc % 16 != 0 || out->kc > (1 << 20))
+    return fail(CG_EINVAL, "kc %d must be 0 or a positive multiple of 16 up to 2^20", out->kc);
+  if (out->row_offset < 0) return fail(CG_EINVAL, "row_offset %lld < 0", (long long)out->row_offset);
+  if (out->workspace && ((uintptr_t)out->workspace & 255))
+    return fail(CG_EINVAL, "workspace must be 256-byte aligned");
+  return CG_OK;
+}
+
+size_t elem_size(int dtype) { return dtype == CG_DTYPE_F64 ? 8 : 4; }
+
+cg::Prec to_prec(int p) {
+  return p == CG_PREC_BF16 ? cg::Prec::BF16 : p == CG_PREC_FP8 ? cg::Prec::FP8 : cg::Prec::Native;
+}
+
+int check_shape(int dtype, int64_t n, int64_t d, int64_t m, int64_t B, const Opts& o) {
+  if (dtype != CG_DTYPE_F32 && dtype != CG_DTYPE_F64) return fail(CG_EINVAL, "unknown dtype %d", dtype);
+  if (n < 1) return fail(CG_EINVAL, "n = %lld < 1", (long long)n);
+  if (d < 1) return fail(CG_EINVAL, "d = %lld < 1", (long long)d);
+  if (m < 1) return fail(CG_EINVAL, "m = %lld < 1", (long long)m);
+  if (B < 1 || B > 0x7fffffffLL) return fail(CG_EINVAL, "B = %lld outside [1, 2^31)", (long long)B);
+  if (d > cg::kMaxD) return fail(CG_EUNSUPPORTED, "d = %lld > %d", (long long)d, cg::kMaxD);
+  if (m > 64LL * 65535) return fail(CG_EUNSUPPORTED, "m = %lld > %d", (long long)m, 64 * 65535);
+  if (n > (1LL << 40)) return fail(CG_EUNSUPPORTED, "n = %lld > 2^40", (long long)n);
+  if (dtype == CG_DTYPE_F64 && o.precision != CG_PREC_NATIVE)
+    return fail(CG_EINVAL, "FP64 data supports only native precision");
+  if ((double)B * (double)d > 4e12) return fail(CG_EUNSUPPORTED, "B * d too large");
+  return CG_OK;
+}
+
+// Forward workspace: [S X unless sx_out][split partials][sorted scratch]
+struct FwdLayout {
+  cg::GsxPlan plan;
+  size_t sx = 0, part = 0, sorted = 0, total = 0;
+};
+
+FwdLayout forward_layout(int dtype, bool csr, int64_t n, int64_t d, int64_t nnz, int64_t m,
+                         int64_t B, const Opts& o) {
+  FwdLayout L;
+  const size_t es = elem_size(dtype);
+  L.plan = cg::plan_gsx(m, B, d, to_prec(o.precision), o.kc, es);
+  const size_t sx_bytes = o.sx_out ? 0 : cg::align256((size_t)B * d * es);
+  const size_t part_bytes = cg::align256((size_t)L.plan.parts * m * d * es);
+  const size_t sorted_bytes =
+      o.sx_algo == CG_SX_SORTED
+          ? cg::align256(cg::sorted_scratch_bytes(csr ? nnz : n, B, cg::sorted_payload_bytes(csr, es)))
+          : 0;
+  L.sx = 0;
+  L.part = sx_bytes;
+  L.sorted = sx_bytes + part_bytes;
+  L.total = sx_bytes + part_bytes + sorted_bytes;
+  return L;
+}
+
+int check_workspace(const Opts& o, size_t need) {
+  if (need == 0) return CG_OK;
+  if (!o.workspace || o.workspace_bytes < need)
+    return fail(CG_ENOSPACE, "workspace of %zu bytes needed, %zu given", need,
+                o.workspace ? o.workspace_bytes : (size_t)0);
+  return CG_OK;
+}
+
+template <typename T>
+int forward_typed(const int32_t* row_ptr, const int32_t* col_idx, const T* X, int64_t ldx,
+                  bool csr, int64_t n, int64_t d, int64_t nnz, int64_t m, int64_t B,
+                  uint64_t seed, T* Y, const Opts& o, const FwdLayout& L) {
+  char* ws = (char*)o.workspace;
+  T* SX = o.sx_out ? (T*)o.sx_out : (T*)(ws + L.sx);
+  T* part = (T*)(ws + L.part);
+  const cg::Key key = cg::key_of(seed);
+  const uint64_t off = (uint64_t)o.row_offset;
+  hipError_t e;
+  int st;
+  if ((st = record(o, 0))) return st;
+  if (o.sx_algo == CG_SX_SORTED) {
+    if ((st = record(o, 1))) return st;
+    void* scratch = ws + L.sorted;
+    e = csr ? cg::launch_sx_csr_sorted<T>(row_ptr, col_idx, X, n, nnz, (int)d, (uint32_t)B, key,
+                                          off, SX, scratch, o.stream)
+            : cg::launch_sx_dense_sorted<T>(X, ldx, n, (int)d, (uint32_t)B, key, off, SX, scratch,
+                                            o.stream);
+    if (e != hipSuccess) return hip_fail(e, "sorted S X");
+  } else {
+    e = cg::launch_fill_zero<T>(SX, (size_t)B * d, o.stream);
+    if (e != hipSuccess) return hip_fail(e, "zero S X");
+    if ((st = record(o, 1))) return st;
+    e = csr ? cg::launch_sx_csr_atomic<T>(row_ptr, col_idx, X, n, nnz, (int)d, (uint32_t)B, key,
+                                          off, SX, o.stream)
+            : cg::launch_sx_dense_atomic<T>(X, ldx, n, (int)d, (uint32_t)B, key, off, SX,
+                                            o.stream);
+    if (e != hipSuccess) return hip_fail(e, "atomic S X");
+  }
+  if ((st = record(o, 2))) return st;
+  e = cg::launch_gsx_partials<T>(L.plan, to_prec(o.precision), SX, B, (int)d, (int)m, key, part,
+                                 o.stream);
+  if (e != hipSuccess) return hip_fail(e, "G (S X)");
+  if ((st = record(o, 3))) return st;
+  e = cg::launch_splitk_reduce<T>(part, L.plan.parts, m * d, Y, o.stream);
+  if (e != hipSuccess) return hip_fail(e, "split reduction");
+  return record(o, 4);
+}
+
+}  // namespace
+
+extern "C" {
+
+void cg_opts_init(cg_opts* opts) {
+  if (!opts) return;
+  memset(opts, 0, sizeof *opts);
+  opts->struct_size = sizeof *opts;
+}
+
+int cg_version(void) { return 100; }
+
+const char* cg_status_string(int status) {
+  switch (status) {
+    case CG_OK: return "CG_OK";
+    case CG_EINVAL: return "CG_EINVAL (invalid argument)";
+    case CG_ENOSPACE: return "CG_ENOSPACE (workspace too small)";
+    case CG_EUNSUPPORTED: return "CG_EUNSUPPORTED (outside this build)";
+    case CG_EHIP: return "CG_EHIP (HIP runtime error)";
+    default: return "unknown status";
+  }
+}
+
+size_t cg_last_error(char* buf, size_t len) {
+  if (buf && len) {
+    const size_t k = g_last_error.size() < len - 1 ? g_last_error.size() : len - 1;
+    memcpy(buf, g_last_error.data(), k);
+    buf[k] = 0;
+  }
+  return g_last_error.size();
+}
+
+int cg_workspace_bytes(int kind, int dtype, int64_t n, int64_t d, int64_t m, int64_t B,
+                       int64_t nnz, const cg_opts* opts, size_t* bytes) {
+  Opts o;
+  int st = read_opts(opts, &o);
+  if (st) return st;
+  if (!bytes) return fail(CG_EINVAL, "bytes is NULL");
+  if ((st = check_shape(dtype, n, d, m, B, o))) return st;
+  switch (kind) {
+    case CG_KIND_CSR:
+      if (nnz < 0) return fail(CG_EINVAL, "nnz = %lld < 0", (long long)nnz);
+      *bytes = forward_layout(dtype, true, n, d, nnz, m, B, o).total;
+      return CG_OK;
+    case CG_KIND_DENSE:
+      *bytes = forward_layout(dtype, false, n, d, 0, m, B, o).total;
+      return CG_OK;
+    case CG_KIND_ADJOINT:
+    case CG_KIND_ADJOINT_CSR:
+      *bytes = cg::align256((size_t)B * d * elem_size(dtype));
+      return CG_OK;
+    default:
+      return fail(CG_EINVAL, "unknown workspace kind %d", kind);
+  }
+}
+
+int cg_sketch_csr(const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int dtype,
+                  int64_t n, int64_t d, int64_t nnz, int64_t m, int64_t B, uint64_t seed, void* Y,
+                  const cg_opts* opts) {
+  Opts o;
+  int st = read_opts(opts, &o);
+  if (st) return st;
+  if ((st = check_shape(dtype, n, d, m, B, o))) return st;
+  if (nnz < 0) return fail(CG_EINVAL, "nnz = %lld < 0", (long long)nnz);
+  if (nnz > 0x7fffffffLL) return fail(CG_EUNSUPPORTED, "nnz = %lld >= 2^31 with int32 indices", (long long)nnz);
+  if (!row_ptr || !Y || (nnz > 0 && (!col_idx || !vals)))
+    return fail(CG_EINVAL, "null pointer argument");
+  if (o.sx_algo == CG_SX_SORTED && n > 0x7fffffffLL)
+    return fail(CG_EUNSUPPORTED, "sorted S X needs n < 2^31");
+  const FwdLayout L = forward_layout(dtype, true, n, d, nnz, m, B, o);
+  if ((st = check_workspace(o, L.total))) return st;
+  if (dtype == CG_DTYPE_F64)
+    return forward_typed<double>(row_ptr, col_idx, (const double*)vals, 0, true, n, d, nnz, m, B,
+                                 seed, (double*)Y, o, L);
+  return forward_typed<float>(row_ptr, col_idx, (const float*)vals, 0, true, n, d, nnz, m, B, seed,
+                              (float*)Y, o, L);
+}
+
+int cg_sketch_dense(const void* X, int64_t ldx, int dtype, int64_t n, int64_t d, int64_t m,
+                    int64_t B, uint64_t seed, void* Y, const cg_opts* opts) {
+  Opts o;
+  int st = read_opts(opts, &o);
+  if (st) return st;
+  if ((st = check_shape(dtype, n, d, m, B, o))) return st;
+  if (ldx < d) return fail(CG_EINVAL, "ldx = %lld < d = %lld", (long long)ldx, (long long)d);
+  if (!X || !Y) return fail(CG_EINVAL, "null pointer argument");
+  if (o.sx_algo == CG_SX_SORTED && n > 0x7fffffffLL)
+    return fail(CG_EUNSUPPORTED, "sorted S X needs n < 2^31");
+  const FwdLayout L = forward_layout(dtype, false, n, d, 0, m, B, o);
+  if ((st = check_workspace(o, L.total))) return st;
+  if (dtype == CG_DTYPE_F64)
+    return forward_typed<double>(nullptr, nullptr, (const double*)X, ldx, false, n, d, 0, m, B,
+                                 seed, (double*)Y, o, L);
+  return forward_typed<float>(nullptr, nullptr, (const float*)X, ldx, false, n, d, 0, m, B, seed,
+                              (float*)Y, o, L);
+}
+
+int cg_sketch_adjoint(const void* dY, int dtype, int64_t n, int64_t d, int64_t m, int64_t B,
+                      uint64_t seed, void* dX, int64_t lddx, const cg_opts* opts) {
+  Opts o;
+  int st = read_opts(opts, &o);
+  if (st) return st;
+  if ((st = check_shape(dtype, n, d, m, B, o))) return st;
+  if (o.precision != CG_PREC_NATIVE) return fail(CG_EINVAL, "adjoint supports native precision only");
+  if (lddx < d) return fail(CG_EINVAL, "lddx = %lld < d = %lld", (long long)lddx, (long long)d);
+  if (!dY || !dX) return fail(CG_EINVAL, "null pointer argument");
+  const size_t need = cg::align256((size_t)B * d * elem_size(dtype));
+  if ((st = check_workspace(o, need))) return st;
+  const cg::Key key = cg::key_of(seed);
+  hipError_t e;
+  if (dtype == CG_DTYPE_F64) {
+    double* Z = (double*)o.workspace;
+    e = cg::launch_gt_dy<double>((const double*)dY, (int)m, (int)d, B, key, Z, o.stream);
+    if (e == hipSuccess)
+      e = cg::launch_gather_dense<double>(Z, n, (int)d, (uint32_t)B, key, (uint64_t)o.row_offset,
+                                          (double*)dX, lddx, o.stream);
+  } else {
+    float* Z = (float*)o.workspace;
+    e = cg::launch_gt_dy<float>((const float*)dY, (int)m, (int)d, B, key, Z, o.stream);
+    if (e == hipSuccess)
+      e = cg::launch_gather_dense<float>(Z, n, (int)d, (uint32_t)B, key, (uint64_t)o.row_offset,
+                                         (float*)dX, lddx, o.stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "adjoint");
+  return CG_OK;
+}
+
+int cg_sketch_adjoint_csr(const int32_t* row_ptr, const int32_t* col_idx, int64_t nnz,
+                          const void* dY, int dtype, int64_t n, int64_t d, int64_t m, int64_t B,
+                          uint64_t seed, void* dvals, const cg_opts* opts) {
+  Opts o;
+  int st = read_opts(opts, &o);
+  if (st) return st;
+  if ((st = check_shape(dtype, n, d, m, B, o))) return st;
+  if (o.precision != CG_PREC_NATIVE) return fail(CG_EINVAL, "adjoint supports native precision only");
+  if (nnz < 0) return fail(CG_EINVAL, "nnz = %lld < 0", (long long)nnz);
+  if (nnz > 0x7fffffffLL) return fail(CG_EUNSUPPORTED, "nnz = %lld >= 2^31 with int32 indices", (long long)nnz);
+  if (!row_ptr || !dY || (nnz > 0 && (!col_idx || !dvals)))
+    return fail(CG_EINVAL, "null pointer argument");
+  const size_t need = cg::align256((size_t)B * d * elem_size(dtype));
+  if ((st = check_workspace(o, need))) return st;
+  const cg::Key key = cg::key_of(seed);
+  hipError_t e;
+  if (dtype == CG_DTYPE_F64) {
+    double* Z = (double*)o.workspace;
+    e = cg::launch_gt_dy<double>((const double*)dY, (int)m, (int)d, B, key, Z, o.stream);
+    if (e == hipSuccess)
+      e = cg::launch_gather_csr<double>(row_ptr, col_idx, Z, n, nnz, (int)d, (uint32_t)B, key,
+                                        (uint64_t)o.row_offset, (double*)dvals, o.stream);
+  } else {
+    float* Z = (float*)o.workspace;
+    e = cg::launch_gt_dy<float>((const float*)dY, (int)m, (int)d, B, key, Z, o.stream);
+    if (e == hipSuccess)
+      e = cg::launch_gather_csr<float>(row_ptr, col_idx, Z, n, nnz, (int)d, (uint32_t)B, key,
+                                       (uint64_t)o.row_offset, (float*)dvals, o.stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "adjoint (CSR)");
+  return CG_OK;
+}
+
+int cg_debug_philox(uint64_t seed, const uint32_t* ctr, int64_t count, uint32_t* out,
+                    void* stream) {
+  if (count < 0 || count > (1LL << 30)) return fail(CG_EINVAL, "count %lld out of range", (long long)count);
+  if (count > 0 && (!ctr || !out)) return fail(CG_EINVAL, "null pointer argument");
+  hipError_t e = cg::launch_debug_philox(cg::key_of(seed), ctr, count, out, (hipStream_t)stream);
+  return e == hipSuccess ? CG_OK : hip_fail(e, "debug philox");
+}
+
+int cg_debug_hash(uint64_t seed, int64_t B, uint64_t row0, int64_t count, uint32_t* h,
+                  int8_t* sigma, void* stream) {
+  if (B < 1 || B > 0x7fffffffLL) return fail(CG_EINVAL, "B = %lld outside [1, 2^31)", (long long)B);
+  if (count < 0 || count > (1LL << 30)) return fail(CG_EINVAL, "count %lld out of range", (long long)count);
+  if (count > 0 && (!h || !sigma)) return fail(CG_EINVAL, "null pointer argument");
+  hipError_t e = cg::launch_debug_hash(cg::key_of(seed), (uint32_t)B, row0, count, h, sigma,
+                                       (hipStream_t)stream);
+  return e == hipSuccess ? CG_OK : hip_fail(e, "debug hash");
+}
+
+int cg_debug_gaussian(uint64_t seed, int64_t m, int64_t b0, int64_t nb, int dtype, void* G,
+                      void* stream) {
+  if (m < 1 || m > (1LL << 24)) return fail(CG_EINVAL, "m = %lld out of range", (long long)m);
+  if (b0 < 0 || nb < 0 || b0 + nb > 0x7fffffffLL) return fail(CG_EINVAL, "column range out of [0, 2^31)");
+  if ((m + 3) / 4 * nb > (1LL << 30)) return fail(CG_EINVAL, "m * nb too large");
+  if (dtype != CG_DTYPE_F32 && dtype != CG_DTYPE_F64) return fail(CG_EINVAL, "unknown dtype %d", dtype);
+  if (nb > 0 && !G) return fail(CG_EINVAL, "null pointer argument");
+  const cg::Key key = cg::key_of(seed);
+  hipError_t e = dtype == CG_DTYPE_F64
+                     ? cg::launch_debug_gaussian<double>(key, m, b0, nb, (double*)G, (hipStream_t)stream)
+                     : cg::launch_debug_gaussian<float>(key, m, b0, nb, (float*)G, (hipStream_t)stream);
+  return e == hipSuccess ? CG_OK : hip_fail(e, "debug gaussian");
+}
+
+}  // extern "C"

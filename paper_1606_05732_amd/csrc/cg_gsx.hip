@@ -1,0 +1,377 @@
+// Y = G (S X): the m x B by B x d product of Section 1.1, on MFMA, with G
+// generated in registers and never written to memory.
+//
+// Work split: the B axis (the contraction) is cut into chunks of kc
+// columns of G; one wavefront owns one chunk, one 64-row group of G and up
+// to 64 columns of S X.  Four wavefronts of a workgroup add their
+// accumulators in a fixed order and write one partial m x d product per
+// workgroup; splitk_reduce_kernel then adds the partials in a fixed order.
+// The result is therefore reproducible bit for bit, and FP32 sums never
+// run over more than kc terms before being combined pairwise-ish.
+//
+// Register tiling (v_mfma_*_16x16xK): lane l has p = l % 16 and
+// kq = l / 16.  In the A operand lane l supplies row p and K slot(s) kq;
+// one Philox4x32 block of counter (b, q) yields the four normals
+// G[4q + t][b], t = 0..3, so the lane owns row quad q = 16 * group + p and
+// feeds four MFMA instructions, one per t: M block t holds the G rows
+// 4 (16 group + p) + t.  The B operand (S X) uses the same K slots, so
+// every generated normal is used exactly once.  D element (4 kq + r, p)
+// of M block t is Y row 4 (16 group + 4 kq + r) + t, column p.
+#include "cg_internal.hpp"
+#include "cg_rng.hpp"
+
+namespace cg {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = v4f;
+};
+template <>
+struct Vec4<double> {
+  using type = v4d;
+};
+
+__device__ __forceinline__ v4f mfma_k4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4d mfma_k4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Sum the four wavefronts' accumulators (wave 0 + 1 + 2 + 3, in that
+// order) and write the workgroup's partial product rows/cols that exist.
+template <typename T, int NB, typename V>
+__device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int wave, int lane,
+                                                   int group, int n0, int m, int d,
+                                                   T* __restrict__ out) {
+  constexpr int R = 16 * NB;   // accumulator values per lane
+  if (wave > 0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          red[((wave - 1) * R + (t * NB + nb) * 4 + r) * 64 + lane] = acc[t][nb][r];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  const int p = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int idx = (t * NB + nb) * 4 + r;
+        T s = acc[t][nb][r];
+        s += red[(0 * R + idx) * 64 + lane];
+        s += red[(1 * R + idx) * 64 + lane];
+        s += red[(2 * R + idx) * 64 + lane];
+        const int row = 4 * (16 * group + 4 * kq + r) + t;
+        const int col = n0 + nb * 16 + p;
+        if (row < m && col < d) out[(size_t)row * d + col] = s;
+      }
+}
+
+// Native precision (FP32 or FP64 inputs, same-type accumulation).
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restrict__ SX, int64_t B,
+                                                              int d, int m, int kc, Key key,
+                                                              T* __restrict__ part) {
+  using V = typename Vec4<T>::type;
+  __shared__ T red[3 * 16 * NB * 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = lane & 15, kq = lane >> 4;
+  const int group = blockIdx.y;
+  const uint32_t q = (uint32_t)(16 * group + p);
+  const int n0 = blockIdx.z * NB * 16;
+  V acc[4][NB];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[t][nb] = V{0, 0, 0, 0};
+  int col[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) col[nb] = n0 + nb * 16 + p;
+
+  const int64_t kbeg = ((int64_t)blockIdx.x * kWaves + wave) * kc;
+  const int64_t kend = min(kbeg + (int64_t)kc, B);
+  for (int64_t kb = kbeg; kb < kend; kb += 4) {
+    const int64_t b = kb + kq;
+    T g[4] = {T(0), T(0), T(0), T(0)};
+    T x[NB];
+    if (b < kend) {
+      box_muller(gauss_block((uint32_t)b, q, key.k0, key.k1), g);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) x[nb] = col[nb] < d ? SX[b * d + col[nb]] : T(0);
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) x[nb] = T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(g[t], x[nb], acc[t][nb]);
+  }
+  block_reduce_store<T, NB, V>(acc, red, wave, lane, group, n0, m, d,
+                               part + (size_t)blockIdx.x * m * d);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Smallest e with amax <= 448 * 2^e, from amax's binary exponent
+// (448 = 0.875 * 2^9); 0 for amax == 0.
+__device__ __forceinline__ int fp8_block_exponent(float amax) {
+  if (!(amax > 0.0f)) return 0;
+  int E;
+  const float f = frexpf(amax, &E);
+  return f <= 0.875f ? E - 9 : E - 8;
+}
+
+__device__ __forceinline__ long pack_fp8x8(const float (&v)[8], float scale) {
+  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0] * scale, v[1] * scale, 0, false);
+  lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2] * scale, v[3] * scale, lo, true);
+  int hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4] * scale, v[5] * scale, 0, false);
+  hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6] * scale, v[7] * scale, hi, true);
+  return (long)(uint32_t)lo | ((long)(uint32_t)hi << 32);
+}
+
+__device__ __forceinline__ v8bf pack_bf16x8(const float (&v)[8]) {
+  v8bf r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = (__bf16)v[e];
+  return r;
+}
+
+// Reduced-precision inputs: BF16 (round to nearest even) or FP8 E4M3 with
+// one power-of-two scale per 128-wide block of B for S X and 2^-6 for G;
+// FP32 accumulation.  K = 32 per MFMA: lane (p, kq) supplies the eight
+// columns b = base + 8 kq + e, e = 0..7, i.e. eight Philox blocks per step.
+template <int NB, bool FP8>
+__global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restrict__ SX,
+                                                            int64_t B, int d, int m, int kc,
+                                                            Key key, float* __restrict__ part) {
+  constexpr int KBLK = FP8 ? 128 : 32;
+  __shared__ float red[3 * 16 * NB * 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = lane & 15, kq = lane >> 4;
+  const int group = blockIdx.y;
+  const uint32_t q = (uint32_t)(16 * group + p);
+  const int n0 = blockIdx.z * NB * 16;
+  v4f acc[4][NB];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
+  int col[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) col[nb] = n0 + nb * 16 + p;
+
+  const int64_t kbeg = ((int64_t)blockIdx.x * kWaves + wave) * kc;
+  const int64_t kend = min(kbeg + (int64_t)kc, B);
+  for (int64_t kb = kbeg; kb < kend; kb += KBLK) {
+    float xscale = 1.0f, yscale = 1.0f;
+    if constexpr (FP8) {
+      // block amax over rows [kb, kb + 128) and all d columns of S X
+      float amax = 0.0f;
+      const int64_t rows = min((int64_t)KBLK, kend - kb);
+      const int64_t cnt = rows * d;
+      const float* blk = SX + kb * d;
+      for (int64_t i = lane; i < cnt; i += 64) amax = fmaxf(amax, fabsf(blk[i]));
+      amax = wave_max(amax);
+      // blocks with amax below 448 * 2^-100 keep the scale 2^100 so that
+      // 2^-e stays finite in FP32
+      const int e = max(fp8_block_exponent(amax), -100);
+      xscale = ldexpf(1.0f, -e);
+      yscale = ldexpf(1.0f, e - 6);
+    }
+    v4f tmp[4][NB];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) tmp[t][nb] = v4f{0, 0, 0, 0};
+#pragma unroll
+    for (int sub = 0; sub < KBLK / 32; ++sub) {
+      const int64_t base = kb + sub * 32 + kq * 8;
+      float g[4][8];
+      float x[NB][8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t b = base + e;
+        float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (b < kend) box_muller(gauss_block((uint32_t)b, q, key.k0, key.k1), z);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) g[t][e] = z[t];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          x[nb][e] = (b < kend && col[nb] < d) ? SX[b * d + col[nb]] : 0.0f;
+      }
+      if constexpr (FP8) {
+        long xa[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) xa[nb] = pack_fp8x8(x[nb], xscale);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const long ga = pack_fp8x8(g[t], 64.0f);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            tmp[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ga, xa[nb], tmp[t][nb], 0, 0, 0);
+        }
+      } else {
+        v8bf xa[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) xa[nb] = pack_bf16x8(x[nb]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const v8bf ga = pack_bf16x8(g[t]);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            tmp[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, xa[nb], tmp[t][nb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[t][nb] += tmp[t][nb] * yscale;
+  }
+  block_reduce_store<float, NB, v4f>(acc, red, wave, lane, group, n0, m, d,
+                                     part + (size_t)blockIdx.x * m * d);
+}
+
+// Y[o] = sum over partials p of part[p][o], in increasing p: four
+// wavefronts each add a contiguous quarter, then the quarters are added in
+// order.  Fixed order, so the result does not depend on timing.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(const T* __restrict__ part,
+                                                                 int64_t P, int64_t md,
+                                                                 T* __restrict__ Y) {
+  __shared__ T s[kWaves][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t o = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t p0 = P * wave / kWaves, p1 = P * (wave + 1) / kWaves;
+  T acc = T(0);
+  if (o < md) {
+    int64_t pp = p0;
+    for (; pp + 4 <= p1; pp += 4) {
+      const T a0 = part[(pp + 0) * md + o], a1 = part[(pp + 1) * md + o];
+      const T a2 = part[(pp + 2) * md + o], a3 = part[(pp + 3) * md + o];
+      acc += a0;
+      acc += a1;
+      acc += a2;
+      acc += a3;
+    }
+    for (; pp < p1; ++pp) acc += part[pp * md + o];
+  }
+  s[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && o < md) Y[o] = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
+}
+
+template <typename T, int NB>
+void launch_native(const GsxPlan& pl, const T* SX, int64_t B, int d, int m, Key key, T* part,
+                   hipStream_t s) {
+  dim3 grid((unsigned)pl.parts, (unsigned)pl.mgroups, (unsigned)pl.ngroups);
+  gsx_native_kernel<T, NB><<<grid, kThreads, 0, s>>>(SX, B, d, m, pl.kc, key, part);
+}
+
+template <int NB, bool FP8>
+void launch_lowp(const GsxPlan& pl, const float* SX, int64_t B, int d, int m, Key key,
+                 float* part, hipStream_t s) {
+  dim3 grid((unsigned)pl.parts, (unsigned)pl.mgroups, (unsigned)pl.ngroups);
+  gsx_lowp_kernel<NB, FP8><<<grid, kThreads, 0, s>>>(SX, B, d, m, pl.kc, key, part);
+}
+
+}  // namespace
+
+GsxPlan plan_gsx(int64_t m, int64_t B, int64_t d, Prec prec, int kc_request, size_t elem) {
+  GsxPlan pl;
+  pl.waves = kWaves;
+  const int max_nb = elem == 8 ? 2 : 4;
+  const int need = (int)((d + 15) / 16);
+  pl.nb = need < max_nb ? need : max_nb;
+  pl.ngroups = (int)((d + 16 * pl.nb - 1) / (16 * pl.nb));
+  pl.mgroups = (int)((m + 63) / 64);
+  const int gran = prec == Prec::FP8 ? 128 : prec == Prec::BF16 ? 32 : 16;
+  int64_t kc = kc_request;
+  if (kc <= 0) {
+    // about 4096 wavefronts (16 per CU) in flight over the whole product
+    const int64_t target = 4096;
+    const int64_t units = (int64_t)pl.mgroups * pl.ngroups;
+    kc = (B * units + target - 1) / target;
+    if (kc > 8192) kc = 8192;
+  }
+  kc = (kc + gran - 1) / gran * gran;
+  if (kc < gran) kc = gran;
+  pl.kc = (int)kc;
+  pl.parts = (B + (int64_t)kWaves * kc - 1) / ((int64_t)kWaves * kc);
+  return pl;
+}
+
+template <typename T>
+hipError_t launch_gsx_partials(const GsxPlan& pl, Prec prec, const T* SX, int64_t B, int d, int m,
+                               Key key, T* part, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    if (pl.nb == 1)
+      launch_native<T, 1>(pl, SX, B, d, m, key, part, s);
+    else
+      launch_native<T, 2>(pl, SX, B, d, m, key, part, s);
+  } else {
+    if (prec == Prec::Native) {
+      switch (pl.nb) {
+        case 1: launch_native<T, 1>(pl, SX, B, d, m, key, part, s); break;
+        case 2: launch_native<T, 2>(pl, SX, B, d, m, key, part, s); break;
+        case 3: launch_native<T, 3>(pl, SX, B, d, m, key, part, s); break;
+        default: launch_native<T, 4>(pl, SX, B, d, m, key, part, s); break;
+      }
+    } else if (prec == Prec::BF16) {
+      switch (pl.nb) {
+        case 1: launch_lowp<1, false>(pl, SX, B, d, m, key, part, s); break;
+        case 2: launch_lowp<2, false>(pl, SX, B, d, m, key, part, s); break;
+        case 3: launch_lowp<3, false>(pl, SX, B, d, m, key, part, s); break;
+        default: launch_lowp<4, false>(pl, SX, B, d, m, key, part, s); break;
+      }
+    } else {
+      switch (pl.nb) {
+        case 1: launch_lowp<1, true>(pl, SX, B, d, m, key, part, s); break;
+        case 2: launch_lowp<2, true>(pl, SX, B, d, m, key, part, s); break;
+        case 3: launch_lowp<3, true>(pl, SX, B, d, m, key, part, s); break;
+        default: launch_lowp<4, true>(pl, SX, B, d, m, key, part, s); break;
+      }
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, hipStream_t s) {
+  splitk_reduce_kernel<T><<<(unsigned)((md + 63) / 64), kThreads, 0, s>>>(part, parts, md, Y);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gsx_partials<float>(const GsxPlan&, Prec, const float*, int64_t, int,
+                                               int, Key, float*, hipStream_t);
+template hipError_t launch_gsx_partials<double>(const GsxPlan&, Prec, const double*, int64_t, int,
+                                                int, Key, double*, hipStream_t);
+template hipError_t launch_splitk_reduce<float>(const float*, int64_t, int64_t, float*,
+                                                hipStream_t);
+template hipError_t launch_splitk_reduce<double>(const double*, int64_t, int64_t, double*,
+                                                 hipStream_t);
+
+}  // namespace cg

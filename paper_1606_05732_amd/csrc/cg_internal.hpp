@@ -1,0 +1,94 @@
+// Host-side launchers shared between the kernel sources and the C ABI.
+// Every launcher only queues work on `stream`; sizes are validated by the
+// caller (cg_capi.hip) before any launcher runs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cg {
+
+struct Key {
+  uint32_t k0, k1;
+};
+inline Key key_of(uint64_t seed) { return Key{(uint32_t)seed, (uint32_t)(seed >> 32)}; }
+
+constexpr int kRowsPerWave = 256;   // rows hashed and handled per wavefront
+constexpr int kMaxD = 1024;         // widest X supported by this build
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---- S X --------------------------------------------------------------
+template <typename T>
+hipError_t launch_fill_zero(T* p, size_t count, hipStream_t s);
+
+template <typename T>
+hipError_t launch_sx_csr_atomic(const int32_t* row_ptr, const int32_t* col_idx, const T* vals,
+                                int64_t n, int64_t nnz, int d, uint32_t B, Key key,
+                                uint64_t row_offset, T* SX, hipStream_t s);
+
+template <typename T>
+hipError_t launch_sx_dense_atomic(const T* X, int64_t ldx, int64_t n, int d, uint32_t B, Key key,
+                                  uint64_t row_offset, T* SX, hipStream_t s);
+
+// Deterministic path: stable counting sort by bucket, then a fixed-order
+// per-bucket reduction.  `count` items (rows for dense X, stored entries for
+// CSR) of `payload` bytes each.
+size_t sorted_scratch_bytes(int64_t count, int64_t B, size_t payload);
+inline size_t sorted_payload_bytes(bool csr, size_t elem) {
+  return csr ? (elem == 8 ? 16 : 8) : 4;
+}
+
+template <typename T>
+hipError_t launch_sx_csr_sorted(const int32_t* row_ptr, const int32_t* col_idx, const T* vals,
+                                int64_t n, int64_t nnz, int d, uint32_t B, Key key,
+                                uint64_t row_offset, T* SX, void* scratch, hipStream_t s);
+
+template <typename T>
+hipError_t launch_sx_dense_sorted(const T* X, int64_t ldx, int64_t n, int d, uint32_t B, Key key,
+                                  uint64_t row_offset, T* SX, void* scratch, hipStream_t s);
+
+// ---- G (S X) -----------------------------------------------------------
+enum class Prec { Native, BF16, FP8 };
+
+struct GsxPlan {
+  int kc;          // columns of G per wavefront
+  int waves;       // wavefronts per workgroup
+  int64_t parts;   // workgroups along B = number of split partials
+  int mgroups;     // 64-row groups of G
+  int ngroups;     // column groups of S X
+  int nb;          // 16-column blocks per wavefront
+};
+
+GsxPlan plan_gsx(int64_t m, int64_t B, int64_t d, Prec prec, int kc_request, size_t elem);
+
+// Partial products part[p] (m x d) of workgroup p along B ...
+template <typename T>
+hipError_t launch_gsx_partials(const GsxPlan& plan, Prec prec, const T* SX, int64_t B, int d,
+                               int m, Key key, T* part, hipStream_t s);
+// ... and Y = sum over p of part[p] in increasing p.
+template <typename T>
+hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, hipStream_t s);
+
+// ---- adjoint ----------------------------------------------------------
+template <typename T>
+hipError_t launch_gt_dy(const T* dY, int m, int d, int64_t B, Key key, T* Z, hipStream_t s);
+
+template <typename T>
+hipError_t launch_gather_dense(const T* Z, int64_t n, int d, uint32_t B, Key key,
+                               uint64_t row_offset, T* dX, int64_t lddx, hipStream_t s);
+
+template <typename T>
+hipError_t launch_gather_csr(const int32_t* row_ptr, const int32_t* col_idx, const T* Z,
+                             int64_t n, int64_t nnz, int d, uint32_t B, Key key,
+                             uint64_t row_offset, T* dvals, hipStream_t s);
+
+// ---- test access ------------------------------------------------------
+hipError_t launch_debug_philox(Key key, const uint32_t* ctr, int64_t count, uint32_t* out,
+                               hipStream_t s);
+hipError_t launch_debug_hash(Key key, uint32_t B, uint64_t row0, int64_t count, uint32_t* h,
+                             int8_t* sigma, hipStream_t s);
+template <typename T>
+hipError_t launch_debug_gaussian(Key key, int64_t m, int64_t b0, int64_t nb, T* G, hipStream_t s);
+
+}  // namespace cg

@@ -1,0 +1,132 @@
+"""The adjoint kernels (Z = G^T dY on MFMA, then the signed row gather) and
+the autograd binding, against the oracle's FP64 adjoint, the adjoint
+identity and central finite differences of the oracle forward."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1606_05732_amd as cg
+from paper_1606_05732_amd import workloads as W
+from tests.gpu_util import csr_to_gpu, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float32: 1e-5, torch.float64: 1e-12}
+NPD = {torch.float32: np.float32, torch.float64: np.float64}
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("n,d,m,B", [(1, 1, 1, 1), (3000, 10, 20, 2000), (5003, 64, 128, 4096),
+                                     (999, 17, 70, 333), (500, 130, 9, 100)])
+def test_dense_adjoint_parity(cuda, dtype, n, d, m, B):
+    rng = np.random.default_rng(n + m)
+    dY = rng.standard_normal((m, d)).astype(NPD[dtype])
+    seed = 41
+    say("adjoint dense", dtype, n, d, m, B)
+    dX = cg.sketch_adjoint(torch.from_numpy(dY).to(cuda), n, m, B, seed)
+    torch.cuda.synchronize()
+    ref = O.adjoint_dense(dY.astype(np.float64), n, d, m, B, seed)
+    assert rel(dX.cpu().numpy(), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_csr_adjoint_parity_and_identity(cuda, dtype):
+    rng = np.random.default_rng(5)
+    n, d, m, B, seed = 7000, 24, 40, 900, 3
+    rp, ci, v = W.csr_bernoulli(rng, n, d, 0.1, dtype=NPD[dtype])
+    dY = rng.standard_normal((m, d)).astype(NPD[dtype])
+    say("adjoint csr", dtype)
+    X = csr_to_gpu(rp, ci, v, n, d, cuda)
+    dv = cg.sketch_adjoint_csr(X, torch.from_numpy(dY).to(cuda), m, B, seed)
+    Y = cg.sketch(X, m, B, seed)
+    torch.cuda.synchronize()
+    ref = O.adjoint_csr(rp, ci, dY.astype(np.float64), n, d, m, B, seed)
+    assert rel(dv.cpu().numpy(), ref) < TOL[dtype]
+    lhs = float(np.sum(dY.astype(np.float64) * Y.cpu().numpy()))
+    rhs = float(np.sum(dv.cpu().numpy().astype(np.float64) * v))
+    assert abs(lhs - rhs) <= 10 * TOL[dtype] * (abs(lhs) + 1)
+
+
+def test_finite_differences_on_slice(cuda):
+    """X[0:4096, 0:8] of the gradient workload as its own input, m = 128,
+    B = 2^19: the GPU adjoint equals the oracle's FP64 adjoint on every
+    entry and central differences (h = 1e-3) of the oracle's forward on a
+    stratified sample of 512 entries (L = <dY, T X> is linear, so the
+    differences are exact up to rounding)."""
+    n, d, m, B, seed = 4096, 8, 128, 1 << 19, 2004
+    rng = np.random.default_rng(1004)
+    X = rng.standard_normal((n, d))
+    dY = rng.standard_normal((m, d))
+    say("fd slice")
+    dX = cg.sketch_adjoint(torch.from_numpy(dY).to(cuda), n, m, B, seed)
+    torch.cuda.synchronize()
+    dX = dX.cpu().numpy()
+    assert rel(dX, O.adjoint_dense(dY, n, d, m, B, seed)) < 1e-12
+    # forward restricted to the buckets the slice touches (G is independent
+    # of X, so this is the same function of X)
+    h, sigma = O.hash_rows(seed, B, np.arange(n, dtype=np.uint64))
+    used = np.unique(h)
+    Gu = np.concatenate([O.gaussian_block(seed, m, int(b), 1) for b in used], axis=1)
+    pos = np.searchsorted(used, h)
+
+    def loss(Z):
+        SX = np.zeros((len(used), d))
+        np.add.at(SX, pos, sigma[:, None] * Z)
+        return float(np.sum(dY * (Gu @ SX)))
+
+    entries = [(int(r), c) for c in range(d) for r in rng.choice(n, 64, replace=False)]
+    fd = O.central_fd(loss, X, entries, 1e-3)
+    got = np.array([dX[r, c] for r, c in entries])
+    assert np.allclose(got, fd, rtol=1e-7, atol=1e-8)
+
+
+def test_autograd_linear_and_quadratic(cuda):
+    rng = np.random.default_rng(8)
+    n, d, m, B, seed = 6000, 16, 32, 777, 12
+    X = torch.from_numpy(rng.standard_normal((n, d))).to(cuda).requires_grad_(True)
+    dY = torch.from_numpy(rng.standard_normal((m, d))).to(cuda)
+    say("autograd")
+    Y = cg.countgauss(X, m, B, seed)
+    (Y * dY).sum().backward()
+    torch.cuda.synchronize()
+    ref = O.adjoint_dense(dY.cpu().numpy(), n, d, m, B, seed)
+    assert rel(X.grad.cpu().numpy(), ref) < 1e-12
+    # L(w) = ||T (X w - y)||^2, T acting on an n-vector
+    Xn = X.detach()
+    w = torch.from_numpy(rng.standard_normal(d)).to(cuda).requires_grad_(True)
+    y = torch.from_numpy(rng.standard_normal(n)).to(cuda)
+    r = (Xn @ w - y)[:, None]
+    loss = (cg.countgauss(r, m, B, seed) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    rn = (Xn.cpu().numpy() @ w.detach().cpu().numpy() - y.cpu().numpy())[:, None]
+    g_ref = Xn.cpu().numpy().T @ O.adjoint_dense(2 * O.sketch_dense(rn, m, B, seed), n, 1, m, B,
+                                                 seed)[:, 0]
+    assert rel(w.grad.cpu().numpy(), g_ref) < 1e-12
+    assert abs(loss.item() - float(np.sum(O.sketch_dense(rn, m, B, seed) ** 2))) < 1e-9 * loss.item()
+
+
+def test_workload4_full_size_adjoint(cuda):
+    """n = 2^22, d = 64, m = 128, B = 2^19, FP32 upstream dY ~ N(0,1): the
+    whole dX against the oracle, plus the gradient of ||T (X w - y)||^2."""
+    w = W.workload4()
+    dY = w.extra["dY"].astype(np.float32)
+    say("workload4 adjoint full")
+    dX = cg.sketch_adjoint(torch.from_numpy(dY).to(cuda), w.n, w.m, w.B, w.seed)
+    torch.cuda.synchronize()
+    ref = O.adjoint_dense(dY.astype(np.float64), w.n, w.d, w.m, w.B, w.seed)
+    assert rel(dX.cpu().numpy(), ref) < 1e-5
+    del dX
+    Xg = torch.from_numpy(w.dense).to(cuda)
+    wt = torch.from_numpy(w.extra["w"].astype(np.float32)).to(cuda).requires_grad_(True)
+    y = torch.from_numpy(w.extra["y"].astype(np.float32)).to(cuda)
+    r = (Xg @ wt - y)[:, None]
+    loss = (cg.countgauss(r, w.m, w.B, w.seed) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    rn = (w.dense.astype(np.float64) @ w.extra["w"].astype(np.float32).astype(np.float64)
+          - w.extra["y"].astype(np.float32))[:, None]
+    g_ref = w.dense.astype(np.float64).T @ O.adjoint_dense(
+        2 * O.sketch_dense(rn, w.m, w.B, w.seed), w.n, 1, w.m, w.B, w.seed)[:, 0]
+    assert rel(wt.grad.cpu().numpy(), g_ref) < 1e-4
