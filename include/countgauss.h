@@ -76,13 +76,22 @@ extern "C" {
  * BF16/FP8) and reduce the split over B in a fixed order.                */
 
 /* ---- algorithm for S X ------------------------------------------------- */
-#define CG_SX_AUTO 0        /* library's choice (the atomic path)           */
+#define CG_SX_AUTO 0        /* library's choice: BINNED for FP32 data when
+                               its bucket ranges fit (d <= 64 for dense X),
+                               ATOMIC otherwise                            */
 #define CG_SX_ATOMIC 1      /* one device-scope atomic add per stored entry;
                                summation order within a bucket varies from
-                               run to run in FP32                           */
-#define CG_SX_SORTED 2      /* rows grouped by bucket (counting sort), each
-                               bucket summed in increasing row order:
-                               bitwise reproducible                         */
+                               run to run                                  */
+#define CG_SX_SORTED 2      /* stable radix sort by bucket, each bucket
+                               summed in increasing row order by one
+                               wavefront: bitwise reproducible             */
+#define CG_SX_BINNED 3      /* FP32 only: split by bucket range, each range
+                               summed in LDS by one workgroup.  CSR sums are
+                               64-bit fixed point with a per-range scale from
+                               the range's max |x| (bitwise reproducible;
+                               entries below max|x| * 2^-(61 - log2 count)
+                               lose precision); dense rows are summed in FP32
+                               (order varies from run to run)              */
 
 /* ---- workspace kinds --------------------------------------------------- */
 #define CG_KIND_CSR 0

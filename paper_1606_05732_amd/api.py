@@ -13,7 +13,8 @@ from . import _lib as L
 
 _PREC = {"native": L.CG_PREC_NATIVE, "fp32": L.CG_PREC_NATIVE, "fp64": L.CG_PREC_NATIVE,
          "bf16": L.CG_PREC_BF16, "fp8": L.CG_PREC_FP8}
-_ALGO = {"auto": L.CG_SX_AUTO, "atomic": L.CG_SX_ATOMIC, "sorted": L.CG_SX_SORTED}
+_ALGO = {"auto": L.CG_SX_AUTO, "atomic": L.CG_SX_ATOMIC, "sorted": L.CG_SX_SORTED,
+         "binned": L.CG_SX_BINNED}
 
 
 @dataclass

@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcountgauss.so")
 ARCH = os.environ.get("CG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["cg_sx_atomic.hip", "cg_sx_sorted.hip", "cg_gsx.hip", "cg_adjoint.hip",
+SOURCES = ["cg_sx_atomic.hip", "cg_sx_sorted.hip", "cg_sx_binned.hip", "cg_gsx.hip", "cg_adjoint.hip",
            "cg_batched.hip", "cg_capi.hip"]
 
 FLAGS = [

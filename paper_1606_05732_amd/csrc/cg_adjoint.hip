@@ -39,6 +39,14 @@ __device__ __forceinline__ v4d mfma_k4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Result row held in accumulator register r for kq = lane / 16: FP32
+// 16x16x4 keeps rows 4 kq .. 4 kq + 3, FP64 16x16x4 rows kq, kq+4, kq+8,
+// kq+12 (measured on gfx950).
+template <typename T>
+__device__ __forceinline__ int d_row(int kq, int r) {
+  return sizeof(T) == 8 ? kq + 4 * r : 4 * kq + r;
+}
+
 // One wavefront computes Z for 16 consecutive buckets b and up to 16 NB
 // columns.  MFMA roles: M = bucket (lane % 16), K = row i of G, N = column
 // of dY.  K slot kq of step s holds G row 4 (4 s + kq) + t for sub-step t,
@@ -78,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void gt_dy_kernel(const T* __restrict__ d
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = b0 + 4 * kq + r;
+      const int64_t row = b0 + d_row<T>(kq, r);
       if (row < B && col[nb] < d) Z[row * d + col[nb]] = acc[nb][r];
     }
 }

@@ -62,7 +62,7 @@ int read_opts(const cg_opts* o, Opts* out) {
   out->events = o->stage_events;
   if (out->precision < CG_PREC_NATIVE || out->precision > CG_PREC_FP8)
     return fail(CG_EINVAL, "unknown precision %d", out->precision);
-  if (out->sx_algo < CG_SX_AUTO || out->sx_algo > CG_SX_SORTED)
+  if (out->sx_algo < CG_SX_AUTO || out->sx_algo > CG_SX_BINNED)
     return fail(CG_EINVAL, "unknown sx_algo %d", out->sx_algo);
   if (out->kc < 0 || out->kc % 16 != 0 || out->kc > (1 << 20))
     return fail(CG_EINVAL, "kc %d must be 0 or a positive multiple of 16 up to 2^20", out->kc);
@@ -93,27 +93,42 @@ int check_shape(int dtype, int64_t n, int64_t d, int64_t m, int64_t B, const Opt
   return CG_OK;
 }
 
-// Forward workspace: [S X unless sx_out][split partials][sorted scratch]
+// The S X algorithm a call runs: AUTO resolves to BINNED for FP32 data
+// whose bucket ranges fit, else ATOMIC; BINNED asked for where it does not
+// apply is an error.
+int resolve_algo(int dtype, bool csr, int64_t n, int64_t d, int64_t B, int requested) {
+  const bool fits = dtype == CG_DTYPE_F32 && cg::bin_geometry(csr, n, (int)d, B).ok;
+  if (requested == CG_SX_AUTO) return fits ? CG_SX_BINNED : CG_SX_ATOMIC;
+  if (requested == CG_SX_BINNED && !fits) return -1;
+  return requested;
+}
+
+// Forward workspace: [S X unless sx_out][split partials][S X scratch]
 struct FwdLayout {
   cg::GsxPlan plan;
-  size_t sx = 0, part = 0, sorted = 0, total = 0;
+  int algo = CG_SX_ATOMIC;
+  size_t sx = 0, part = 0, scratch = 0, total = 0;
 };
 
 FwdLayout forward_layout(int dtype, bool csr, int64_t n, int64_t d, int64_t nnz, int64_t m,
                          int64_t B, const Opts& o) {
   FwdLayout L;
   const size_t es = elem_size(dtype);
+  L.algo = resolve_algo(dtype, csr, n, d, B, o.sx_algo);
   L.plan = cg::plan_gsx(m, B, d, to_prec(o.precision), o.kc, es);
   const size_t sx_bytes = o.sx_out ? 0 : cg::align256((size_t)B * d * es);
   const size_t part_bytes = cg::align256((size_t)L.plan.parts * m * d * es);
-  const size_t sorted_bytes =
-      o.sx_algo == CG_SX_SORTED
-          ? cg::align256(cg::sorted_scratch_bytes(csr ? nnz : n, B, cg::sorted_payload_bytes(csr, es)))
-          : 0;
+  size_t scratch_bytes = 0;
+  if (L.algo == CG_SX_SORTED)
+    scratch_bytes = cg::align256(
+        cg::sorted_scratch_bytes(csr ? nnz : n, B, cg::sorted_payload_bytes(csr, es)));
+  else if (L.algo == CG_SX_BINNED)
+    scratch_bytes = cg::align256(
+        cg::binned_scratch_bytes(cg::bin_geometry(csr, n, (int)d, B), csr ? nnz : n));
   L.sx = 0;
   L.part = sx_bytes;
-  L.sorted = sx_bytes + part_bytes;
-  L.total = sx_bytes + part_bytes + sorted_bytes;
+  L.scratch = sx_bytes + part_bytes;
+  L.total = sx_bytes + part_bytes + scratch_bytes;
   return L;
 }
 
@@ -137,9 +152,18 @@ int forward_typed(const int32_t* row_ptr, const int32_t* col_idx, const T* X, in
   hipError_t e;
   int st;
   if ((st = record(o, 0))) return st;
-  if (o.sx_algo == CG_SX_SORTED) {
+  if (L.algo == CG_SX_BINNED) {
+    if constexpr (sizeof(T) == 4) {
+      void* scratch = ws + L.scratch;
+      e = csr ? cg::launch_sx_binned_csr(row_ptr, col_idx, X, n, nnz, (int)d, (uint32_t)B, key, off,
+                                         SX, scratch, o.stream, o.events)
+              : cg::launch_sx_binned_dense(X, ldx, n, (int)d, (uint32_t)B, key, off, SX, scratch,
+                                           o.stream, o.events);
+      if (e != hipSuccess) return hip_fail(e, "binned S X");
+    }
+  } else if (L.algo == CG_SX_SORTED) {
     if ((st = record(o, 1))) return st;
-    void* scratch = ws + L.sorted;
+    void* scratch = ws + L.scratch;
     e = csr ? cg::launch_sx_csr_sorted<T>(row_ptr, col_idx, X, n, nnz, (int)d, (uint32_t)B, key,
                                           off, SX, scratch, o.stream)
             : cg::launch_sx_dense_sorted<T>(X, ldx, n, (int)d, (uint32_t)B, key, off, SX, scratch,
@@ -207,10 +231,18 @@ int cg_workspace_bytes(int kind, int dtype, int64_t n, int64_t d, int64_t m, int
   switch (kind) {
     case CG_KIND_CSR:
       if (nnz < 0) return fail(CG_EINVAL, "nnz = %lld < 0", (long long)nnz);
-      *bytes = forward_layout(dtype, true, n, d, nnz, m, B, o).total;
+      {
+        const FwdLayout L = forward_layout(dtype, true, n, d, nnz, m, B, o);
+        if (L.algo < 0) return fail(CG_EUNSUPPORTED, "binned S X does not apply to these sizes");
+        *bytes = L.total;
+      }
       return CG_OK;
     case CG_KIND_DENSE:
-      *bytes = forward_layout(dtype, false, n, d, 0, m, B, o).total;
+      {
+        const FwdLayout L = forward_layout(dtype, false, n, d, 0, m, B, o);
+        if (L.algo < 0) return fail(CG_EUNSUPPORTED, "binned S X does not apply to these sizes");
+        *bytes = L.total;
+      }
       return CG_OK;
     case CG_KIND_ADJOINT:
     case CG_KIND_ADJOINT_CSR:
@@ -235,6 +267,7 @@ int cg_sketch_csr(const int32_t* row_ptr, const int32_t* col_idx, const void* va
   if (o.sx_algo == CG_SX_SORTED && n > 0x7fffffffLL)
     return fail(CG_EUNSUPPORTED, "sorted S X needs n < 2^31");
   const FwdLayout L = forward_layout(dtype, true, n, d, nnz, m, B, o);
+  if (L.algo < 0) return fail(CG_EUNSUPPORTED, "binned S X needs FP32 data and at most %d bucket ranges", cg::kBinMaxRangesCsr);
   if ((st = check_workspace(o, L.total))) return st;
   if (dtype == CG_DTYPE_F64)
     return forward_typed<double>(row_ptr, col_idx, (const double*)vals, 0, true, n, d, nnz, m, B,
@@ -254,6 +287,7 @@ int cg_sketch_dense(const void* X, int64_t ldx, int dtype, int64_t n, int64_t d,
   if (o.sx_algo == CG_SX_SORTED && n > 0x7fffffffLL)
     return fail(CG_EUNSUPPORTED, "sorted S X needs n < 2^31");
   const FwdLayout L = forward_layout(dtype, false, n, d, 0, m, B, o);
+  if (L.algo < 0) return fail(CG_EUNSUPPORTED, "binned S X needs FP32 data, d <= 64 and at most %d bucket ranges", cg::kBinMaxRangesDense);
   if ((st = check_workspace(o, L.total))) return st;
   if (dtype == CG_DTYPE_F64)
     return forward_typed<double>(nullptr, nullptr, (const double*)X, ldx, false, n, d, 0, m, B,

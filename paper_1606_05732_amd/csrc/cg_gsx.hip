@@ -16,7 +16,8 @@
 // feeds four MFMA instructions, one per t: M block t holds the G rows
 // 4 (16 group + p) + t.  The B operand (S X) uses the same K slots, so
 // every generated normal is used exactly once.  D element (4 kq + r, p)
-// of M block t is Y row 4 (16 group + 4 kq + r) + t, column p.
+// of M block t is Y row 4 (16 group + 4 kq + r) + t, column p (FP64: the
+// D rows of a lane are kq + 4 r instead, see d_row).
 #include "cg_internal.hpp"
 #include "cg_rng.hpp"
 
@@ -49,6 +50,15 @@ __device__ __forceinline__ v4d mfma_k4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Row of the 16x16 result block held in accumulator register r of a lane
+// with kq = lane / 16 (the column is lane % 16).  The FP32 16x16x4 and the
+// K=32 variants keep four consecutive rows per lane; the FP64 16x16x4
+// interleaves them (measured on gfx950).
+template <typename T>
+__device__ __forceinline__ int d_row(int kq, int r) {
+  return sizeof(T) == 8 ? kq + 4 * r : 4 * kq + r;
+}
+
 // Sum the four wavefronts' accumulators (wave 0 + 1 + 2 + 3, in that
 // order) and write the workgroup's partial product rows/cols that exist.
 template <typename T, int NB, typename V>
@@ -79,7 +89,7 @@ __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int 
         s += red[(0 * R + idx) * 64 + lane];
         s += red[(1 * R + idx) * 64 + lane];
         s += red[(2 * R + idx) * 64 + lane];
-        const int row = 4 * (16 * group + 4 * kq + r) + t;
+        const int row = 4 * (16 * group + d_row<T>(kq, r)) + t;
         const int col = n0 + nb * 16 + p;
         if (row < m && col < d) out[(size_t)row * d + col] = s;
       }

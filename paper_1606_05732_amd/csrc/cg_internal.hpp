@@ -48,6 +48,34 @@ template <typename T>
 hipError_t launch_sx_dense_sorted(const T* X, int64_t ldx, int64_t n, int d, uint32_t B, Key key,
                                   uint64_t row_offset, T* SX, void* scratch, hipStream_t s);
 
+// Exclusive scan of a[0 .. len) in place; sums needs scan_sums_len(len)
+// entries of scratch.
+int64_t scan_sums_len(int64_t len);
+hipError_t launch_exclusive_scan(uint32_t* a, int64_t len, uint32_t* sums, hipStream_t s);
+
+// Binned path (FP32): bucket ranges of 2^bp_shift buckets whose S X slice
+// fits in LDS, R ranges, ntiles row tiles.
+constexpr int kBinMaxRangesCsr = 2048;
+constexpr int kBinMaxRangesDense = 4096;
+struct BinGeom {
+  int bp_shift = 0;
+  int R = 0;
+  int64_t ntiles = 0;
+  size_t lds_bytes = 0;
+  bool ok = false;
+};
+BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B);
+size_t binned_scratch_bytes(const BinGeom& g, int64_t count);
+// `events`, if non-NULL, is the caller's stage-event array; events[1] is
+// recorded after the split plan (counts and scan).
+hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
+                                int64_t n, int64_t nnz, int d, uint32_t B, Key key,
+                                uint64_t row_offset, float* SX, void* scratch, hipStream_t s,
+                                void* const* events);
+hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d, uint32_t B,
+                                  Key key, uint64_t row_offset, float* SX, void* scratch,
+                                  hipStream_t s, void* const* events);
+
 // ---- G (S X) -----------------------------------------------------------
 enum class Prec { Native, BF16, FP8 };
 

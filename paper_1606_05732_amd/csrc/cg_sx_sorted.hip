@@ -402,6 +402,17 @@ hipError_t radix_sort(Scratch& s, int64_t count, uint32_t B, hipStream_t st) {
 
 }  // namespace
 
+int64_t scan_sums_len(int64_t len) { return (len + kScanChunk - 1) / kScanChunk; }
+
+hipError_t launch_exclusive_scan(uint32_t* a, int64_t len, uint32_t* sums, hipStream_t st) {
+  if (len <= 0) return hipSuccess;
+  const int64_t ns = scan_sums_len(len);
+  scan_sums_kernel<<<(unsigned)ns, kThreads, 0, st>>>(a, len, sums);
+  scan_top_kernel<<<1, kThreads, 0, st>>>(sums, ns);
+  scan_apply_kernel<<<(unsigned)ns, kThreads, 0, st>>>(a, len, sums);
+  return hipGetLastError();
+}
+
 size_t sorted_scratch_bytes(int64_t count, int64_t B, size_t payload) {
   return scratch_bytes(count, B, payload);
 }

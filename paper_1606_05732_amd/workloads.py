@@ -32,7 +32,9 @@ def csr_bernoulli(rng, n, d, p, dtype=np.float32, absolute=False):
     i.i.d. Bernoulli(p) sparsity over an n x d matrix, values N(0,1) (or
     |N(0,1)| when absolute)."""
     total = n * d
-    if p >= 1.0:
+    if p <= 0.0:
+        pos = np.zeros(0, np.int64)
+    elif p >= 1.0:
         pos = np.arange(total, dtype=np.int64)
     else:
         pieces = []

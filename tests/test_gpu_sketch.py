@@ -35,15 +35,23 @@ SHAPES = [
 ]
 
 
+def _binned_applies(dtype, d, csr):
+    return dtype == torch.float32 and (csr or d <= 64)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 @pytest.mark.parametrize("n,d,m,B", SHAPES)
-@pytest.mark.parametrize("algo", ["atomic", "sorted"])
+@pytest.mark.parametrize("algo", ["atomic", "sorted", "binned", "auto"])
 def test_dense_parity(cuda, dtype, n, d, m, B, algo):
     X = _dense_case(n, d, n + d, dtype)
     seed = 1234 + n
     say("dense", dtype, n, d, m, B, algo)
     Xg = torch.from_numpy(X).to(cuda)
     SX = torch.empty((B, d), dtype=dtype, device=cuda)
+    if algo == "binned" and not _binned_applies(dtype, d, False):
+        with pytest.raises(cg.CountGaussError):
+            cg.sketch(Xg, m, B, seed, algo=algo)
+        return
     Y = cg.sketch(Xg, m, B, seed, algo=algo, sx_out=SX)
     torch.cuda.synchronize()
     sx_ref = O.sx_dense(X.astype(np.float64), seed, B)
@@ -57,7 +65,7 @@ def test_dense_parity(cuda, dtype, n, d, m, B, algo):
     (1, 1, 1.0, 1, 1), (4097, 10, 0.01, 20, 2000), (20000, 32, 0.05, 64, 4096),
     (3001, 17, 0.3, 70, 555), (1000, 200, 0.2, 16, 64), (777, 8, 0.0, 5, 100),
 ])
-@pytest.mark.parametrize("algo", ["atomic", "sorted"])
+@pytest.mark.parametrize("algo", ["atomic", "sorted", "binned", "auto"])
 def test_csr_parity(cuda, dtype, n, d, p, m, B, algo):
     rng = np.random.default_rng(n * 7 + d)
     rp, ci, v = W.csr_bernoulli(rng, n, d, p, dtype=NPD[dtype], absolute=True)
@@ -65,6 +73,10 @@ def test_csr_parity(cuda, dtype, n, d, p, m, B, algo):
     say("csr", dtype, n, d, p, m, B, algo, "nnz", len(ci))
     X = csr_to_gpu(rp, ci, v, n, d, cuda)
     SX = torch.empty((B, d), dtype=dtype, device=cuda)
+    if algo == "binned" and not _binned_applies(dtype, d, True):
+        with pytest.raises(cg.CountGaussError):
+            cg.sketch(X, m, B, seed, algo=algo)
+        return
     Y = cg.sketch(X, m, B, seed, algo=algo, sx_out=SX)
     torch.cuda.synchronize()
     sx_ref = O.sx_csr(rp, ci, v, n, d, seed, B)
@@ -100,6 +112,48 @@ def test_strided_dense_input(cuda):
     Y = cg.sketch(Xg, 16, 300, 8)
     torch.cuda.synchronize()
     assert rel(Y.cpu().numpy(), O.sketch_dense(X[:, 5:29], 16, 300, 8)) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["csr", "dense"])
+def test_binned_csr_is_bitwise_reproducible(cuda, kind):
+    if kind == "dense":
+        pytest.skip("dense binned sums in FP32 in a run-dependent order (documented)")
+    rng = np.random.default_rng(12)
+    n, d, m, B, seed = 200000, 32, 64, 65536, 6
+    rp, ci, v = W.csr_bernoulli(rng, n, d, 0.05, dtype=np.float32, absolute=True)
+    X = csr_to_gpu(rp, ci, v, n, d, cuda)
+    say("binned determinism")
+    sxs = []
+    for _ in range(3):
+        SX = torch.empty((B, d), dtype=torch.float32, device=cuda)
+        cg.sketch(X, m, B, seed, algo="binned", sx_out=SX)
+        sxs.append(SX)
+    torch.cuda.synchronize()
+    assert torch.equal(sxs[0], sxs[1]) and torch.equal(sxs[0], sxs[2])
+    assert rel(sxs[0].cpu().numpy(), O.sx_csr(rp, ci, v, n, d, seed, B)) < 2e-7
+
+
+@pytest.mark.parametrize("algo", ["atomic", "binned", "sorted"])
+def test_nan_and_inf_reach_their_bucket(cuda, algo):
+    rng = np.random.default_rng(13)
+    n, d, m, B, seed = 5000, 8, 16, 512, 7
+    rp, ci, v = W.csr_bernoulli(rng, n, d, 0.3, dtype=np.float32)
+    v[10] = np.nan
+    v[20] = np.inf
+    X = csr_to_gpu(rp, ci, v, n, d, cuda)
+    say("nonfinite", algo)
+    SX = torch.empty((B, d), dtype=torch.float32, device=cuda)
+    Y = cg.sketch(X, m, B, seed, algo=algo, sx_out=SX)
+    torch.cuda.synchronize()
+    with np.errstate(invalid="ignore"):
+        sx_ref = O.sx_csr(rp, ci, v, n, d, seed, B)
+        y_ref = O.gaussian_matrix(seed, m, B) @ sx_ref
+    got = SX.cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(sx_ref))
+    assert np.array_equal(np.isinf(got), np.isinf(sx_ref))
+    fin = np.isfinite(sx_ref)
+    assert rel(got[fin], sx_ref[fin]) < 2e-6
+    assert np.array_equal(np.isfinite(Y.cpu().numpy()), np.isfinite(y_ref))
 
 
 @pytest.mark.parametrize("kind", ["csr", "dense"])
@@ -152,19 +206,22 @@ def test_workload2_full_size_csr(cuda):
     say("workload2 full csr", c.nnz)
     X = csr_to_gpu(c.row_ptr, c.col_idx, c.vals, c.n, c.d, cuda)
     SX = torch.empty((w.B, c.d), dtype=torch.float32, device=cuda)
-    y = cg.sketch(X, w.m, w.B, w.seed, sx_out=SX)
-    torch.cuda.synchronize()
     sx_ref = O.sx_csr(c.row_ptr, c.col_idx, c.vals, c.n, c.d, w.seed, w.B)
-    assert rel(SX.cpu().numpy(), sx_ref) < 2e-6
     ref = O.gaussian_matrix(w.seed, w.m, w.B) @ sx_ref
-    assert rel(y.cpu().numpy(), ref) < 1e-5
+    for algo in ("auto", "atomic", "binned", "sorted"):
+        y = cg.sketch(X, w.m, w.B, w.seed, sx_out=SX, algo=algo)
+        torch.cuda.synchronize()
+        assert rel(SX.cpu().numpy(), sx_ref) < 2e-6, algo
+        assert rel(y.cpu().numpy(), ref) < 1e-5, algo
 
 
 def test_workload2_full_size_dense(cuda):
     """Dense n = 2^22, d = 32, FP32, m = 64, B = 65536."""
     w = W.workload2_dense()
     say("workload2 full dense")
-    y = cg.sketch(torch.from_numpy(w.dense).to(cuda), w.m, w.B, w.seed)
-    torch.cuda.synchronize()
     ref = O.sketch_dense(w.dense, w.m, w.B, w.seed)
-    assert rel(y.cpu().numpy(), ref) < 1e-5
+    Xg = torch.from_numpy(w.dense).to(cuda)
+    for algo in ("auto", "atomic", "binned", "sorted"):
+        y = cg.sketch(Xg, w.m, w.B, w.seed, algo=algo)
+        torch.cuda.synchronize()
+        assert rel(y.cpu().numpy(), ref) < 1e-5, algo
