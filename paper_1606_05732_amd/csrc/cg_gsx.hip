@@ -265,33 +265,39 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
                                      part + (size_t)blockIdx.x * m * d);
 }
 
-// Y[o] = sum over partials p of part[p][o], in increasing p: four
-// wavefronts each add a contiguous quarter, then the quarters are added in
-// order.  Fixed order, so the result does not depend on timing.
+// Y[o] = sum over partials p of part[p][o]: 16 wavefronts each add a
+// contiguous sixteenth of the partials (eight loads in flight), then the
+// sixteen sums are added in order.  Fixed order, so the result does not
+// depend on timing.
+constexpr int kRedWaves = 16;
 template <typename T>
-__global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(const T* __restrict__ part,
-                                                                 int64_t P, int64_t md,
-                                                                 T* __restrict__ Y) {
-  __shared__ T s[kWaves][64];
+__global__ __launch_bounds__(64 * kRedWaves) void splitk_reduce_kernel(const T* __restrict__ part,
+                                                                      int64_t P, int64_t md,
+                                                                      T* __restrict__ Y) {
+  __shared__ T s[kRedWaves][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t o = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t p0 = P * wave / kWaves, p1 = P * (wave + 1) / kWaves;
+  const int64_t p0 = P * wave / kRedWaves, p1 = P * (wave + 1) / kRedWaves;
   T acc = T(0);
   if (o < md) {
     int64_t pp = p0;
-    for (; pp + 4 <= p1; pp += 4) {
-      const T a0 = part[(pp + 0) * md + o], a1 = part[(pp + 1) * md + o];
-      const T a2 = part[(pp + 2) * md + o], a3 = part[(pp + 3) * md + o];
-      acc += a0;
-      acc += a1;
-      acc += a2;
-      acc += a3;
+    for (; pp + 8 <= p1; pp += 8) {
+      T a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = part[(pp + u) * md + o];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += a[u];
     }
     for (; pp < p1; ++pp) acc += part[pp * md + o];
   }
   s[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0 && o < md) Y[o] = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
+  if (wave == 0 && o < md) {
+    T y = s[0][lane];
+#pragma unroll
+    for (int w = 1; w < kRedWaves; ++w) y += s[w][lane];
+    Y[o] = y;
+  }
 }
 
 template <typename T, int NB>
@@ -371,7 +377,7 @@ hipError_t launch_gsx_partials(const GsxPlan& pl, Prec prec, const T* SX, int64_
 
 template <typename T>
 hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, hipStream_t s) {
-  splitk_reduce_kernel<T><<<(unsigned)((md + 63) / 64), kThreads, 0, s>>>(part, parts, md, Y);
+  splitk_reduce_kernel<T><<<(unsigned)((md + 63) / 64), 64 * kRedWaves, 0, s>>>(part, parts, md, Y);
   return hipGetLastError();
 }
 

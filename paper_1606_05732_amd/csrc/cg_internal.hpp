@@ -56,7 +56,7 @@ hipError_t launch_exclusive_scan(uint32_t* a, int64_t len, uint32_t* sums, hipSt
 // Binned path (FP32): bucket ranges of 2^bp_shift buckets whose S X slice
 // fits in LDS, R ranges, ntiles row tiles.
 constexpr int kBinMaxRangesCsr = 2048;
-constexpr int kBinMaxRangesDense = 4096;
+constexpr int kBinMaxRangesDense = 2048;
 struct BinGeom {
   int bp_shift = 0;
   int R = 0;

@@ -7,13 +7,17 @@
 // two passes over the data without any floating-point atomic:
 //
 //  1. split: the buckets are cut into R ranges of Bp = 2^k consecutive
-//     buckets whose S X slice fits in LDS.  A workgroup takes a tile of
-//     16384 rows, counts its items per range (bin_count), an exclusive scan
-//     over (range, tile) gives every tile a private window in each range's
-//     item list, and bin_scatter writes the items there.
-//  2. reduce: one workgroup per range accumulates its items into an LDS
-//     slice and writes the slice -- every bucket of S X is written exactly
-//     once, so no zero fill is needed.
+//     buckets whose S X slice fits in LDS.  bin_count counts every row
+//     tile's items per range; one exclusive scan over (range, tile) gives
+//     each tile a private window in each range's item list; bin_scatter_*
+//     fills the windows.  A scatter workgroup takes its tile in rounds of
+//     2048 rows: it counts the round's items per range, places them in LDS
+//     grouped by range, and writes each range's run with consecutive
+//     lanes on consecutive addresses (scattered 8-byte stores would cost
+//     partial-line writes to HBM).
+//  2. reduce: one workgroup per range accumulates its items in LDS and
+//     writes the slice; every bucket of S X is written exactly once, so no
+//     zero fill is needed.
 //
 // CSR items are (cell = local bucket * d + column, sigma v).  They are
 // summed as 64-bit fixed-point integers with ds_add_u64: the range's scale
@@ -23,12 +27,11 @@
 // holds a NaN or infinity is summed with float atomics instead (same
 // propagation as the atomic path).
 //
-// Dense items are (row | sign << 31, local bucket).  In the reduce the four
-// wavefronts of a workgroup own disjoint buckets (lb mod 4), read every
-// item of the range, gather the rows they own whole (lanes = columns) and
-// add them with plain LDS read-add-write; up to 64 / LPR rows are added at
-// once, each into its own copy of the slice, and the copies are added in a
-// fixed order at the end.
+// Dense items are (row | sign << 31, local bucket).  The reduce sorts a
+// range's items by bucket in LDS (counting sort); each wavefront then
+// streams the rows of a contiguous group of buckets -- lanes across
+// columns, 16 rows in flight -- summing in registers, and adds a bucket's
+// sum into the LDS slice when the bucket changes.
 #include "cg_internal.hpp"
 #include "cg_rng.hpp"
 
@@ -36,13 +39,47 @@ namespace cg {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = 4;
-constexpr int kTileRows = 16384;
-constexpr int kSubRows = kWaves * kRowsPerWave;   // rows staged per pass in the CSR scatter
+constexpr int kThreads = 1024;                 // count and reduce kernels
+constexpr int kWaves = kThreads / 64;
+constexpr int kSThreads = 256;                 // scatter kernels: several per CU, so
+constexpr int kSWaves = kSThreads / 64;        // one's barriers overlap another's work
+constexpr int kTileRows = 16384;               // rows per split tile
+constexpr int kRPL = 8;                        // rows per lane per scatter round
+constexpr int kRoundRows = kRPL * kSThreads;   // rows per scatter round
+constexpr int kSegBatch = 16;                  // entries a lane loads at once
+constexpr size_t kScatterLds = 40 * 1024;      // LDS target of a scatter workgroup
+constexpr int kDenseCap = 8192;                // items sorted per dense reduce pass
 
-// One dynamic LDS area per kernel, typed at each use.
 extern __shared__ __align__(16) unsigned char dyn_lds[];
+
+// Exclusive scan over the NT threads of the block; *total gets the sum.
+template <int NT = kThreads>
+__device__ uint32_t block_exscan(uint32_t v, uint32_t* s_w, uint32_t* total) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    uint32_t t = lane < NW ? s_w[lane] : 0u;
+#pragma unroll
+    for (int off = 1; off < NW; off <<= 1) {
+      const uint32_t y = __shfl_up(t, off, 64);
+      if (lane >= off) t += y;
+    }
+    if (lane < NW) s_w[lane] = t;
+  }
+  __syncthreads();
+  const uint32_t before = wave ? s_w[wave - 1] : 0u;
+  *total = s_w[NW - 1];
+  __syncthreads();
+  return before + x - v;
+}
 
 // ------------------------------------------------------------------ count
 template <bool CSR>
@@ -54,19 +91,36 @@ __global__ __launch_bounds__(kThreads) void bin_count_kernel(
   __syncthreads();
   const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
   const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
-  for (int64_t r = t0 + 4 * (int64_t)threadIdx.x; r < t1; r += 4 * kThreads) {
-    uint32_t hv[4];
-    hash4(row_offset + (uint64_t)r, B, key.k0, key.k1, hv);
-    int32_t ptr[5];
+  // four rows per thread per step, four steps per batch; every step's
+  // row_ptr loads go out before any is used.  (Indices are clamped instead
+  // of guarded: a guarded load becomes a branch with its own wait.)
+  constexpr int S = 4;
+  for (int64_t b0 = t0; b0 < t1; b0 += (int64_t)S * 4 * kThreads) {
+    int32_t ptr[S][5];
     if (CSR) {
 #pragma unroll
-      for (int j = 0; j < 5; ++j) ptr[j] = r + j <= t1 ? min(max(row_ptr[r + j], 0), nnz) : 0;
+      for (int s = 0; s < S; ++s) {
+        const int64_t r = b0 + 4 * ((int64_t)s * kThreads + threadIdx.x);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) ptr[s][j] = row_ptr[min(r + j, t1)];
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) ptr[s][j] = min(max(ptr[s][j], 0), nnz);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (r + j < t1) {
-        const uint32_t len = CSR ? (uint32_t)max(ptr[j + 1] - ptr[j], 0) : 1u;
-        if (len) atomicAdd(&s_cnt[hash_bucket(hv[j]) >> bp_shift], len);
+    for (int s = 0; s < S; ++s) {
+      const int64_t r = b0 + 4 * ((int64_t)s * kThreads + threadIdx.x);
+      if (r >= t1) continue;
+      uint32_t hv[4];
+      hash4(row_offset + (uint64_t)r, B, key.k0, key.k1, hv);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (r + j < t1) {
+          const uint32_t len = CSR ? (uint32_t)max(ptr[s][j + 1] - ptr[s][j], 0) : 1u;
+          if (len) atomicAdd(&s_cnt[hash_bucket(hv[j]) >> bp_shift], len);
+        }
       }
     }
   }
@@ -74,125 +128,270 @@ __global__ __launch_bounds__(kThreads) void bin_count_kernel(
   for (int p = threadIdx.x; p < R; p += kThreads) hist[(int64_t)p * ntiles + blockIdx.x] = s_cnt[p];
 }
 
-// Per-range base offset of this tile and the number of slots it owns.
+// Per-range base offset of this tile's window and its end (never past the
+// item buffer, even if a malformed CSR made the counts exceed nnz).
 __device__ __forceinline__ void load_windows(const uint32_t* __restrict__ offs, int R,
-                                             int64_t ntiles, uint32_t total, uint32_t* s_base,
-                                             uint32_t* s_lim) {
+                                             int64_t ntiles, uint32_t total, uint32_t* g_base,
+                                             uint32_t* g_next) {
   const int64_t len = (int64_t)R * ntiles;
-  for (int p = threadIdx.x; p < R; p += kThreads) {
+  for (int p = threadIdx.x; p < R; p += kSThreads) {
     const int64_t idx = (int64_t)p * ntiles + blockIdx.x;
-    const uint32_t base = offs[idx];
-    // never past the item buffer, even if a malformed CSR made the counts
-    // exceed nnz
-    const uint32_t next = min(idx + 1 < len ? offs[idx + 1] : total, total);
-    s_base[p] = base;
-    s_lim[p] = next > base ? next - base : 0u;
+    g_base[p] = offs[idx];
+    g_next[p] = min(idx + 1 < len ? offs[idx + 1] : total, total);
   }
 }
 
-// ------------------------------------------------------------------ scatter
-__global__ __launch_bounds__(kThreads) void bin_scatter_csr_kernel(
+// LDS of the scatter kernels: stage | per-range arrays | block scan.
+struct ScatterLds {
+  uint2* stage;
+  uint32_t *g_base, *g_next, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
+  uint32_t* s_w;    // kSWaves
+};
+
+// Items a scatter round may stage: what is left of the LDS target after
+// the per-range arrays (at least one round of dense rows).
+__host__ __device__ inline int stage_cap(int R) {
+  const int64_t left = (int64_t)kScatterLds - (int64_t)7 * R * 4 - kSWaves * 4;
+  int cap = (int)((left > 0 ? left : 0) / 8) & ~255;
+  return cap < kRoundRows ? kRoundRows : cap;
+}
+
+__host__ __device__ inline size_t scatter_lds_bytes(int R) {
+  return (size_t)stage_cap(R) * 8 + (size_t)7 * R * 4 + kSWaves * 4;
+}
+
+__device__ __forceinline__ ScatterLds carve_scatter(int R) {
+  ScatterLds L;
+  unsigned char* p = dyn_lds;
+  L.stage = (uint2*)p;
+  p += (size_t)stage_cap(R) * 8;
+  uint32_t* q = (uint32_t*)p;
+  L.g_base = q;
+  L.g_next = q + R;
+  L.g_run = q + 2 * R;
+  L.r_cnt = q + 3 * R;
+  L.r_off = q + 4 * R;
+  L.r_fill = q + 5 * R;
+  L.r_max = q + 6 * R;
+  L.s_w = q + 7 * R;
+  return L;
+}
+
+__device__ __forceinline__ void clear_ranges(const ScatterLds& L, int R) {
+  for (int p = threadIdx.x; p < R; p += kSThreads) {
+    L.g_run[p] = 0;
+    L.r_cnt[p] = 0;
+    L.r_fill[p] = 0;
+    L.r_max[p] = 0;
+  }
+}
+
+// Exclusive offsets of the round's per-range counts (each thread scans
+// ceil(R / kSThreads) consecutive ranges); returns the total.
+__device__ __forceinline__ uint32_t round_offsets(const ScatterLds& L, int R) {
+  const int per = (R + kSThreads - 1) / kSThreads;
+  const int b = (int)threadIdx.x * per;
+  uint32_t local = 0;
+  for (int k = 0; k < per; ++k)
+    if (b + k < R) local += L.r_cnt[b + k];
+  uint32_t E;
+  uint32_t run = block_exscan<kSThreads>(local, L.s_w, &E);
+  for (int k = 0; k < per; ++k) {
+    if (b + k < R) {
+      L.r_off[b + k] = run;
+      run += L.r_cnt[b + k];
+    }
+  }
+  __syncthreads();
+  return E;
+}
+
+// Write the round's staged items (grouped by range in stage[0 .. E)) to
+// their windows -- consecutive lanes on consecutive slots of a run -- and
+// advance each range's write cursor.  `swap` puts the stage's second word
+// first (dense items).
+__device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t E, bool swap,
+                                            uint2* __restrict__ items) {
+  for (uint32_t i = threadIdx.x; i < E; i += kSThreads) {
+    const uint2 it = L.stage[i];
+    const uint32_t p = it.x >> 16;
+    const uint32_t pos = L.g_base[p] + L.g_run[p] + (i - L.r_off[p]);
+    if (pos < L.g_next[p])
+      items[pos] = swap ? make_uint2(it.y, it.x & 0xffffu) : make_uint2(it.x & 0xffffu, it.y);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < R; p += kSThreads) {
+    L.g_run[p] += L.r_cnt[p];
+    L.r_cnt[p] = 0;
+    L.r_fill[p] = 0;
+  }
+}
+
+// ------------------------------------------------------------------ scatter (CSR)
+// A round takes 2048 rows, eight consecutive rows per lane, whose entries
+// form one contiguous segment of col_idx/vals.  A lane loads its segment in
+// batches of 16 entries (all loads of a batch in flight together), finds
+// each entry's row by comparing with the row starts, and reserves slots per
+// row, not per entry.
+__global__ __launch_bounds__(kSThreads) void bin_scatter_csr_kernel(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ vals, int64_t n, int32_t nnz, int d, uint32_t B, Key key,
     uint64_t row_offset, int bp_shift, int R, int64_t ntiles, const uint32_t* __restrict__ offs,
     uint32_t total, uint2* __restrict__ items, uint32_t* __restrict__ hmax) {
-  uint32_t* smem = (uint32_t*)dyn_lds;
-  uint32_t* s_base = smem;
-  uint32_t* s_lim = smem + R;
-  uint32_t* s_cnt = smem + 2 * R;
-  uint32_t* s_max = smem + 3 * R;
-  uint32_t* s_hash = smem + 4 * R;                                  // kWaves * 256
-  int32_t* s_ptr = (int32_t*)(s_hash + kWaves * kRowsPerWave);     // kWaves * 257
-  load_windows(offs, R, ntiles, total, s_base, s_lim);
-  for (int p = threadIdx.x; p < R; p += kThreads) {
-    s_cnt[p] = 0;
-    s_max[p] = 0;
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint32_t* sh = s_hash + wave * kRowsPerWave;
-  int32_t* sp = s_ptr + wave * (kRowsPerWave + 1);
+  const ScatterLds L = carve_scatter(R);
+  const uint32_t cap = (uint32_t)stage_cap(R);
+  load_windows(offs, R, ntiles, total, L.g_base, L.g_next);
+  clear_ranges(L, R);
   const uint32_t bmask = (1u << bp_shift) - 1u;
   const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
   const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
-  for (int64_t sub = t0; sub < t1; sub += kSubRows) {
+  for (int64_t round = t0; round < t1; round += kRoundRows) {
     __syncthreads();
-    const int64_t r0 = sub + (int64_t)wave * kRowsPerWave;
-    const int nr = r0 < t1 ? (int)min((int64_t)kRowsPerWave, t1 - r0) : 0;
-    if (nr > 0) {
-      uint32_t hv[4];
-      hash4(row_offset + (uint64_t)r0 + 4 * (uint64_t)lane, B, key.k0, key.k1, hv);
+    const int64_t r = round + (int64_t)kRPL * threadIdx.x;
+    int32_t rp[kRPL + 1];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (4 * lane + t < nr) sh[4 * lane + t] = hv[t];
-      for (int i = lane; i <= nr; i += 64) sp[i] = min(max(row_ptr[r0 + i], 0), nnz);
+    for (int j = 0; j <= kRPL; ++j) rp[j] = row_ptr[min(r + j, t1)];
+#pragma unroll
+    for (int j = 0; j <= kRPL; ++j) rp[j] = min(max(rp[j], 0), nnz);
+#pragma unroll
+    for (int j = 1; j <= kRPL; ++j) rp[j] = max(rp[j], rp[j - 1]);   // malformed rows -> empty
+    uint32_t hv[kRPL];
+#pragma unroll
+    for (int j = 0; j < kRPL; j += 4) {
+      uint32_t h4[4] = {0u, 0u, 0u, 0u};
+      if (r + j < t1) hash4(row_offset + (uint64_t)(r + j), B, key.k0, key.k1, h4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) hv[j + t] = h4[t];
+    }
+    uint32_t len[kRPL];
+#pragma unroll
+    for (int j = 0; j < kRPL; ++j) {
+      len[j] = (uint32_t)(rp[j + 1] - rp[j]);   // zero for rows at or past t1
+      if (len[j]) atomicAdd(&L.r_cnt[hash_bucket(hv[j]) >> bp_shift], len[j]);
     }
     __syncthreads();
-    if (nr == 0) continue;
-    const int32_t kb = sp[0], ke = sp[nr];
-    for (int32_t base = kb; base < ke; base += 64) {
-      const int32_t k = base + lane;
-      if (k < ke) {
-        const int32_t c = col_idx[k];
-        const float v = vals[k];
-        int lo = 0;
+    const uint32_t E = round_offsets(L, R);
+    const bool staged = E <= cap;
+    // per row: first slot of its entries (stage index, or window index)
+    uint32_t slot0[kRPL], maxb[kRPL];
 #pragma unroll
-        for (int step = kRowsPerWave / 2; step > 0; step >>= 1)
-          if (lo + step < nr && sp[lo + step] <= k) lo += step;
-        const uint32_t hp = sh[lo];
-        const uint32_t bucket = hash_bucket(hp);
+    for (int j = 0; j < kRPL; ++j) {
+      const uint32_t p = hash_bucket(hv[j]) >> bp_shift;
+      const uint32_t b = len[j] ? atomicAdd(&L.r_fill[p], len[j]) : 0u;
+      slot0[j] = staged ? L.r_off[p] + b : L.g_base[p] + L.g_run[p] + b;
+      maxb[j] = 0u;
+    }
+    const int32_t seg0 = rp[0], seg1 = rp[kRPL];
+    int32_t span = seg1 - seg0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) span = max(span, __shfl_xor(span, off, 64));
+    for (int32_t t = 0; t < span; t += kSegBatch) {
+      int32_t cc[kSegBatch];
+      float vv[kSegBatch];
+      // span > 0, so nnz >= 1 and the clamped index is always readable
+#pragma unroll
+      for (int u = 0; u < kSegBatch; ++u) {
+        const int32_t k = seg1 > seg0 ? min(seg0 + t + u, seg1 - 1) : 0;
+        cc[u] = col_idx[k];
+        vv[u] = vals[k];
+      }
+#pragma unroll
+      for (int u = 0; u < kSegBatch; ++u) {
+        const int32_t k = seg0 + t + u;
+        if (k >= seg1) break;
+        int j = 0;
+#pragma unroll
+        for (int q = 1; q < kRPL; ++q) j += k >= rp[q];
+        uint32_t hj = hv[0], sj = slot0[0];
+        int32_t rs = rp[0];
+#pragma unroll
+        for (int q = 1; q < kRPL; ++q)
+          if (j == q) {
+            hj = hv[q];
+            sj = slot0[q];
+            rs = rp[q];
+          }
+        const uint32_t bucket = hash_bucket(hj);
         const uint32_t p = bucket >> bp_shift;
+        const int32_t c = cc[u];
         const bool ok = (unsigned)c < (unsigned)d;
         const uint32_t cell = ok ? (bucket & bmask) * (uint32_t)d + (uint32_t)c : 0u;
-        const float sv = ok ? (hash_negative(hp) ? -v : v) : 0.0f;
-        const uint32_t slot = atomicAdd(&s_cnt[p], 1u);
-        if (slot < s_lim[p]) items[s_base[p] + slot] = make_uint2(cell, __float_as_uint(sv));
-        atomicMax(&s_max[p], __float_as_uint(fabsf(sv)));
+        const float sv = ok ? (hash_negative(hj) ? -vv[u] : vv[u]) : 0.0f;
+        const uint32_t slot = sj + (uint32_t)(k - rs);
+        const uint32_t mb = __float_as_uint(fabsf(sv));
+#pragma unroll
+        for (int q = 0; q < kRPL; ++q)
+          if (j == q) maxb[q] = max(maxb[q], mb);
+        if (staged) {
+          if (slot < E) L.stage[slot] = make_uint2((p << 16) | cell, __float_as_uint(sv));
+        } else {
+          // a round too large for the stage (very long rows): direct stores
+          if (slot < L.g_next[p]) items[slot] = make_uint2(cell, __float_as_uint(sv));
+        }
       }
     }
+#pragma unroll
+    for (int j = 0; j < kRPL; ++j)
+      if (len[j]) atomicMax(&L.r_max[hash_bucket(hv[j]) >> bp_shift], maxb[j]);
+    __syncthreads();
+    flush_stage(L, R, staged ? E : 0u, false, items);
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < R; p += kThreads) hmax[(int64_t)p * ntiles + blockIdx.x] = s_max[p];
+  for (int q = threadIdx.x; q < R; q += kSThreads) hmax[(int64_t)q * ntiles + blockIdx.x] = L.r_max[q];
 }
 
-__global__ __launch_bounds__(kThreads) void bin_scatter_dense_kernel(
+// ------------------------------------------------------------------ scatter (dense)
+__global__ __launch_bounds__(kSThreads) void bin_scatter_dense_kernel(
     int64_t n, uint32_t B, Key key, uint64_t row_offset, int bp_shift, int R, int64_t ntiles,
     const uint32_t* __restrict__ offs, uint32_t total, uint2* __restrict__ items) {
-  uint32_t* smem = (uint32_t*)dyn_lds;
-  uint32_t* s_base = smem;
-  uint32_t* s_lim = smem + R;
-  uint32_t* s_cnt = smem + 2 * R;
-  load_windows(offs, R, ntiles, total, s_base, s_lim);
-  for (int p = threadIdx.x; p < R; p += kThreads) s_cnt[p] = 0;
-  __syncthreads();
+  const ScatterLds L = carve_scatter(R);
+  load_windows(offs, R, ntiles, total, L.g_base, L.g_next);
+  clear_ranges(L, R);
   const uint32_t bmask = (1u << bp_shift) - 1u;
   const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
   const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
-  for (int64_t r = t0 + 4 * (int64_t)threadIdx.x; r < t1; r += 4 * kThreads) {
-    uint32_t hv[4];
-    hash4(row_offset + (uint64_t)r, B, key.k0, key.k1, hv);
+  // rounds of kRoundRows rows: one item per row, within the stage capacity
+  for (int64_t round = t0; round < t1; round += kRoundRows) {
+    __syncthreads();
+    const int64_t r = round + (int64_t)kRPL * threadIdx.x;
+    uint32_t hv[kRPL];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kRPL; j += 4) {
+      uint32_t h4[4] = {0u, 0u, 0u, 0u};
+      if (r + j < t1) hash4(row_offset + (uint64_t)(r + j), B, key.k0, key.k1, h4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) hv[j + t] = h4[t];
+    }
+#pragma unroll
+    for (int j = 0; j < kRPL; ++j)
+      if (r + j < t1) atomicAdd(&L.r_cnt[hash_bucket(hv[j]) >> bp_shift], 1u);
+    __syncthreads();
+    const uint32_t E = round_offsets(L, R);   // <= kRoundRows <= stage capacity
+#pragma unroll
+    for (int j = 0; j < kRPL; ++j) {
       if (r + j < t1) {
         const uint32_t bucket = hash_bucket(hv[j]);
         const uint32_t p = bucket >> bp_shift;
-        const uint32_t slot = atomicAdd(&s_cnt[p], 1u);
-        if (slot < s_lim[p])
-          items[s_base[p] + slot] =
-              make_uint2((uint32_t)(r + j) | (hv[j] & 0x80000000u), bucket & bmask);
+        const uint32_t slot = atomicAdd(&L.r_fill[p], 1u);
+        if (slot < L.r_cnt[p] && L.r_off[p] + slot < E)
+          L.stage[L.r_off[p] + slot] = make_uint2(
+              (p << 16) | (bucket & bmask), (uint32_t)(r + j) | (hv[j] & 0x80000000u));
       }
     }
+    __syncthreads();
+    flush_stage(L, R, E, true, items);
   }
 }
 
 // ------------------------------------------------------------------ reduce
 __device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* s_red) {
-  s_red[threadIdx.x] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s_red[threadIdx.x] = max(s_red[threadIdx.x], s_red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  const uint32_t r = s_red[0];
+  uint32_t r = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) r = max(r, s_red[w]);
   __syncthreads();
   return r;
 }
@@ -211,13 +410,13 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(
     const uint32_t* __restrict__ hmax, int64_t ntiles, int R, uint32_t total, uint32_t B, int d,
     int bp_shift, float* __restrict__ SX) {
   unsigned long long* s_acc = (unsigned long long*)dyn_lds;
-  __shared__ uint32_t s_red[kThreads];
+  __shared__ uint32_t s_red[kWaves];
   const int p = blockIdx.x;
   const int cells = (1 << bp_shift) * d;
   for (int i = threadIdx.x; i < cells; i += kThreads) s_acc[i] = 0ull;
   uint32_t mx = 0;
   for (int64_t t = threadIdx.x; t < ntiles; t += kThreads) mx = max(mx, hmax[(int64_t)p * ntiles + t]);
-  const uint32_t amax_bits = block_max_u32(mx, s_red);   // also orders the zero fill
+  const uint32_t amax_bits = block_max_u32(mx, s_red);   // its barrier also orders the zero fill
   uint32_t start, end;
   range_of(offs, p, R, ntiles, total, &start, &end);
   if (amax_bits >= 0x7f800000u) {
@@ -244,13 +443,14 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(
   while (lg < 32 && (1u << lg) < count) ++lg;
   const int f = 61 - E - lg;
   const double scale = ldexp(1.0, f), inv = ldexp(1.0, -f);
+  constexpr int UR = 8;
   uint32_t i = start + threadIdx.x;
-  for (; i + 3 * kThreads < end; i += 4 * kThreads) {
-    uint2 it[4];
+  for (; i + (UR - 1) * kThreads < end; i += UR * kThreads) {
+    uint2 it[UR];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) it[u] = items[i + u * kThreads];
+    for (int u = 0; u < UR; ++u) it[u] = items[i + u * kThreads];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < UR; ++u)
       if (it[u].x < (uint32_t)cells)
         atomicAdd(&s_acc[it[u].x],
                   (unsigned long long)__double2ll_rn((double)__uint_as_float(it[u].y) * scale));
@@ -267,60 +467,110 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(
   }
 }
 
+// Dense LDS: slice Bp*d floats | rows and their buckets (kDenseCap) |
+// cnt, off, fill (Bp each) | block scan
+__host__ __device__ inline size_t dense_reduce_lds_bytes(int Bp, int d) {
+  return (size_t)Bp * d * 4 + (size_t)kDenseCap * 6 + (size_t)3 * Bp * 4 + kWaves * 4;
+}
+
 template <int LPR>
 __global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t n, const uint2* __restrict__ items,
     const uint32_t* __restrict__ offs, int64_t ntiles, int R, uint32_t total, uint32_t B, int d,
     int bp_shift, float* __restrict__ SX) {
-  constexpr int RPP = 64 / LPR;   // rows added per instruction, one slice copy each
-  constexpr int U = 4;            // instructions' rows gathered before adding
-  float* s_acc = (float*)dyn_lds;
-  const int p = blockIdx.x;
+  constexpr int RPP = 64 / LPR;                // rows per instruction (one per lane group)
+  constexpr int U = RPP >= 8 ? 4 : 16 / RPP;   // row loads in flight per lane group
+  constexpr int PER = kDenseCap / kThreads;    // items held per thread
   const int Bp = 1 << bp_shift;
   const int cells = Bp * d;
-  for (int i = threadIdx.x; i < RPP * cells; i += kThreads) s_acc[i] = 0.0f;
-  __syncthreads();
-  uint32_t start, end;
-  range_of(offs, p, R, ntiles, total, &start, &end);
+  float* slice = (float*)dyn_lds;
+  uint32_t* rows = (uint32_t*)(slice + cells);
+  uint16_t* rb = (uint16_t*)(rows + kDenseCap);
+  uint32_t* cnt = (uint32_t*)(rb + kDenseCap);
+  uint32_t* off = cnt + Bp;
+  uint32_t* fill = off + Bp;
+  uint32_t* s_w = fill + Bp;
+  const int p = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = lane / LPR, c = lane % LPR;
   const bool cok = c < d;
-  float* mycopy = s_acc + j * cells;
-  for (uint32_t base = start; base < end; base += 64) {
-    const uint32_t i = base + lane;
-    uint2 it = make_uint2(0u, 0xffffffffu);
-    if (i < end) it = items[i];
-    const bool mine = i < end && it.y < (uint32_t)Bp && (int)(it.y % kWaves) == wave &&
-                      (int64_t)(it.x & 0x7fffffffu) < n;
-    uint64_t mask = __ballot(mine);
-    while (mask) {
-      float xv[U];
-      uint32_t lbv[U];
-      bool ok[U];
+  const int cc = cok ? c : 0;
+  // wave w owns the contiguous buckets [lb0, lb1)
+  const int lb0 = (int)(((int64_t)Bp * wave) / kWaves), lb1 = (int)(((int64_t)Bp * (wave + 1)) / kWaves);
+  for (int i = threadIdx.x; i < cells; i += kThreads) slice[i] = 0.0f;
+  uint32_t start, end;
+  range_of(offs, p, R, ntiles, total, &start, &end);
+  for (uint32_t c0 = start; c0 < end; c0 += kDenseCap) {
+    const uint32_t nit = min(end - c0, (uint32_t)kDenseCap);
+    for (int b = threadIdx.x; b < Bp; b += kThreads) {
+      cnt[b] = 0;
+      fill[b] = 0;
+    }
+    __syncthreads();
+    uint2 it[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) it[u] = items[c0 + min(threadIdx.x + u * kThreads, nit - 1)];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const bool ok = threadIdx.x + u * kThreads < nit && it[u].y < (uint32_t)Bp &&
+                      (int64_t)(it[u].x & 0x7fffffffu) < n;
+      if (!ok) it[u].y = 0xffffffffu;
+      else atomicAdd(&cnt[it[u].y], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the bucket counts (Bp <= 1024: one per thread)
+    uint32_t tot;
+    const uint32_t ex = block_exscan(threadIdx.x < (unsigned)Bp ? cnt[threadIdx.x] : 0u, s_w, &tot);
+    if (threadIdx.x < (unsigned)Bp) off[threadIdx.x] = ex;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (it[u].y != 0xffffffffu) {
+        const uint32_t pos = off[it[u].y] + atomicAdd(&fill[it[u].y], 1u);
+        if (pos < (uint32_t)kDenseCap) {
+          rows[pos] = it[u].x;
+          rb[pos] = (uint16_t)it[u].y;
+        }
+      }
+    }
+    __syncthreads();
+    // the wave streams the rows of its buckets (contiguous after the sort),
+    // lane group j taking every RPP-th row, U rows in flight; a running sum
+    // per lane is added into the slice whenever the bucket changes
+    const uint32_t s = lb0 < Bp ? off[lb0] : 0u;
+    const uint32_t e = lb1 < Bp ? off[lb1] : min(tot, (uint32_t)kDenseCap);
+    float acc = 0.0f;
+    int cur = -1;
+    for (uint32_t i = s + j; i < max(e, s + j); i += RPP * U) {
+      uint32_t rs[U];
+      int bk[U];
+      float x[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        uint64_t mm = mask;
-        for (int k = 0; k < u * RPP + j && mm; ++k) mm &= mm - 1;
-        const int src = mm ? __ffsll((unsigned long long)mm) - 1 : 0;
-        const uint32_t rs = __shfl(it.x, src, 64);
-        lbv[u] = __shfl(it.y, src, 64);
-        ok[u] = mm != 0 && cok;
-        const float x = ok[u] ? X[(int64_t)(rs & 0x7fffffffu) * ldx + c] : 0.0f;
-        xv[u] = (rs >> 31) ? -x : x;
+        const uint32_t ii = min(i + u * RPP, e > s ? e - 1 : s);
+        rs[u] = rows[ii];
+        bk[u] = i + u * RPP < e ? (int)rb[ii] : -1;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ok[u]) mycopy[lbv[u] * d + c] += xv[u];
-      for (int k = 0; k < U * RPP && mask; ++k) mask &= mask - 1;
+      for (int u = 0; u < U; ++u) x[u] = X[(int64_t)(rs[u] & 0x7fffffffu) * ldx + cc];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (bk[u] < 0) continue;
+        if (bk[u] != cur) {
+          if (cur >= 0 && cok) atomicAdd(&slice[cur * d + c], acc);
+          cur = bk[u];
+          acc = 0.0f;
+        }
+        acc += (rs[u] >> 31) ? -x[u] : x[u];
+      }
     }
+    if (cur >= 0 && cok) atomicAdd(&slice[cur * d + c], acc);
+    __syncthreads();
   }
   __syncthreads();
-  for (int cc = threadIdx.x; cc < cells; cc += kThreads) {
-    float s = s_acc[cc];
-#pragma unroll
-    for (int jj = 1; jj < RPP; ++jj) s += s_acc[jj * cells + cc];
-    const int64_t bucket = ((int64_t)p << bp_shift) + cc / d;
-    if (bucket < B) SX[bucket * d + cc % d] = s;
+  for (int q = threadIdx.x; q < cells; q += kThreads) {
+    const int64_t bucket = ((int64_t)p << bp_shift) + q / d;
+    if (bucket < B) SX[bucket * d + q % d] = slice[q];
   }
 }
 
@@ -335,7 +585,7 @@ struct Carve {
   uint2* items;
 };
 
-Carve carve(void* base, const BinGeom& g, int64_t count) {
+Carve carve(void* base, const BinGeom& g) {
   char* p = (char*)base;
   Carve c;
   const int64_t hl = (int64_t)g.R * g.ntiles;
@@ -349,24 +599,32 @@ Carve carve(void* base, const BinGeom& g, int64_t count) {
   return c;
 }
 
+// Kernels using more than 64 KB of LDS say so before their launch.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 48 * 1024) return hipSuccess;   // headroom for static LDS
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
 }  // namespace
 
 BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B) {
   BinGeom g;
   int shift = 0;
   if (csr) {
-    while (shift < 30 && ((int64_t)2 << shift) * d <= 4096) ++shift;   // int64 cells, 32 KB
+    while (shift < 30 && ((int64_t)2 << shift) * d <= 8192) ++shift;   // int64 cells, 64 KB
     g.lds_bytes = (size_t)(1 << shift) * d * 8;
   } else {
-    const int rpp = 64 / lanes_per_row(d);
-    while (shift < 30 && (int64_t)rpp * ((int64_t)2 << shift) * d <= 8192) ++shift;  // 32 KB
-    g.lds_bytes = (size_t)rpp * (1 << shift) * d * 4;
+    while (shift < 10 && ((int64_t)2 << shift) * d <= 16384) ++shift;  // float cells, 64 KB
+    g.lds_bytes = dense_reduce_lds_bytes(1 << shift, d);
   }
   g.bp_shift = shift;
   g.R = (int)((B + ((int64_t)1 << shift) - 1) >> shift);
   g.ntiles = (n + kTileRows - 1) / kTileRows;
   g.ok = g.R <= (csr ? kBinMaxRangesCsr : kBinMaxRangesDense) && d <= (csr ? kMaxD : 64) &&
-         n < ((int64_t)1 << 31) && g.R * g.ntiles < ((int64_t)1 << 30);
+         n < ((int64_t)1 << 31) && (int64_t)g.R * g.ntiles < ((int64_t)1 << 30) &&
+         scatter_lds_bytes(g.R) <= 96 * 1024;
   return g;
 }
 
@@ -381,15 +639,17 @@ hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, 
                                 uint64_t row_offset, float* SX, void* scratch, hipStream_t s,
                                 void* const* events) {
   const BinGeom g = bin_geometry(true, n, d, B);
-  Carve c = carve(scratch, g, nnz);
+  Carve c = carve(scratch, g);
   const int64_t hl = (int64_t)g.R * g.ntiles;
+  const size_t sl = scatter_lds_bytes(g.R);
+  hipError_t e;
+  if ((e = allow_lds(bin_scatter_csr_kernel, sl)) != hipSuccess) return e;
+  if ((e = allow_lds(bin_reduce_csr_kernel, g.lds_bytes)) != hipSuccess) return e;
   bin_count_kernel<true><<<(unsigned)g.ntiles, kThreads, g.R * 4, s>>>(
       row_ptr, n, (int32_t)nnz, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist);
-  hipError_t e = launch_exclusive_scan(c.hist, hl, c.sums, s);
-  if (e != hipSuccess) return e;
+  if ((e = launch_exclusive_scan(c.hist, hl, c.sums, s)) != hipSuccess) return e;
   if (events && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
-  const size_t smem = (size_t)g.R * 16 + kWaves * kRowsPerWave * 4 + kWaves * (kRowsPerWave + 1) * 4;
-  bin_scatter_csr_kernel<<<(unsigned)g.ntiles, kThreads, smem, s>>>(
+  bin_scatter_csr_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(
       row_ptr, col_idx, vals, n, (int32_t)nnz, d, B, key, row_offset, g.bp_shift, g.R, g.ntiles,
       c.hist, (uint32_t)nnz, c.items, c.hmax);
   bin_reduce_csr_kernel<<<(unsigned)g.R, kThreads, g.lds_bytes, s>>>(
@@ -401,25 +661,33 @@ hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d,
                                   Key key, uint64_t row_offset, float* SX, void* scratch,
                                   hipStream_t s, void* const* events) {
   const BinGeom g = bin_geometry(false, n, d, B);
-  Carve c = carve(scratch, g, n);
+  Carve c = carve(scratch, g);
   const int64_t hl = (int64_t)g.R * g.ntiles;
+  const size_t sl = scatter_lds_bytes(g.R);
+  hipError_t e;
+  if ((e = allow_lds(bin_scatter_dense_kernel, sl)) != hipSuccess) return e;
   bin_count_kernel<false><<<(unsigned)g.ntiles, kThreads, g.R * 4, s>>>(
       nullptr, n, 0, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist);
-  hipError_t e = launch_exclusive_scan(c.hist, hl, c.sums, s);
-  if (e != hipSuccess) return e;
+  if ((e = launch_exclusive_scan(c.hist, hl, c.sums, s)) != hipSuccess) return e;
   if (events && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
-  bin_scatter_dense_kernel<<<(unsigned)g.ntiles, kThreads, (size_t)g.R * 12, s>>>(
+  bin_scatter_dense_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(
       n, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist, (uint32_t)n, c.items);
   const unsigned gr = (unsigned)g.R;
+  const size_t rl = g.lds_bytes;
+#define CG_DENSE_REDUCE(L)                                                                       \
+  if ((e = allow_lds(bin_reduce_dense_kernel<L>, rl)) != hipSuccess) return e;                   \
+  bin_reduce_dense_kernel<L><<<gr, kThreads, rl, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, \
+                                                      (uint32_t)n, B, d, g.bp_shift, SX);
   switch (lanes_per_row(d)) {
-    case 1: bin_reduce_dense_kernel<1><<<gr, kThreads, g.lds_bytes, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, (uint32_t)n, B, d, g.bp_shift, SX); break;
-    case 2: bin_reduce_dense_kernel<2><<<gr, kThreads, g.lds_bytes, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, (uint32_t)n, B, d, g.bp_shift, SX); break;
-    case 4: bin_reduce_dense_kernel<4><<<gr, kThreads, g.lds_bytes, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, (uint32_t)n, B, d, g.bp_shift, SX); break;
-    case 8: bin_reduce_dense_kernel<8><<<gr, kThreads, g.lds_bytes, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, (uint32_t)n, B, d, g.bp_shift, SX); break;
-    case 16: bin_reduce_dense_kernel<16><<<gr, kThreads, g.lds_bytes, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, (uint32_t)n, B, d, g.bp_shift, SX); break;
-    case 32: bin_reduce_dense_kernel<32><<<gr, kThreads, g.lds_bytes, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, (uint32_t)n, B, d, g.bp_shift, SX); break;
-    default: bin_reduce_dense_kernel<64><<<gr, kThreads, g.lds_bytes, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, (uint32_t)n, B, d, g.bp_shift, SX); break;
+    case 1: CG_DENSE_REDUCE(1) break;
+    case 2: CG_DENSE_REDUCE(2) break;
+    case 4: CG_DENSE_REDUCE(4) break;
+    case 8: CG_DENSE_REDUCE(8) break;
+    case 16: CG_DENSE_REDUCE(16) break;
+    case 32: CG_DENSE_REDUCE(32) break;
+    default: CG_DENSE_REDUCE(64) break;
   }
+#undef CG_DENSE_REDUCE
   return hipGetLastError();
 }
 
