@@ -3,15 +3,19 @@
 
 Default workload: CSR X with n = 2^24 rows, d = 32 columns, density 5%
 (about 26.8M stored entries, values |N(0,1)|, FP32), m = 64, B = 65536 --
-the FP32-at-scale workload.  One step is one whole T.X call (zero S X,
-atomic S X, split MFMA contraction with in-register G, fixed-order
-reduction) on inputs already resident in HBM.
+the FP32-at-scale workload.  One step is one whole T.X call on inputs
+already resident in HBM: S X (binned: count, scan, scatter, reduce), the
+split MFMA contraction with in-register G, and its fixed-order reduction.
 
 Prints ONE JSON line on stdout (everything else goes to stderr):
   value        nnz(X) / wall time per step (nnz/s)
-  roofline     the S X kernel (the dominant one): algorithmic bytes per
-               launch / its average duration from HIP events recorded by the
-               library on the launch stream, against the 8 TB/s HBM peak
+  roofline     the S X stage (the dominant one; its four kernels run back to
+               back): algorithmic bytes per launch / its average duration
+               from HIP events recorded by the library on the launch stream,
+               against the 8 TB/s HBM peak; `traffic` is the stage's HBM
+               bytes per launch from committed rocprofv3 FETCH_SIZE /
+               WRITE_SIZE counters scaled by a plain-copy calibration, or
+               null if the kernel sources changed since they were taken
   cpu_baseline the FP64 oracle on the host cores, same workload
   ladder       the G.(S X) precision ladder on the dense spiky workload
                (n = 2^22, d = 64, m = 64, B = 262144): time per step and
@@ -31,8 +35,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_FP32_TFLOPS = 157.3
 METRIC = "T·X nnz/sec and % HBM roofline at 1 GPU; fused BF16/FP8 vs FP32 at stated error"
-COUNTERS = os.path.join(ROOT, "profiles", "sx_csr_atomic_counters.json")
-SX_SOURCE = os.path.join(ROOT, "paper_1606_05732_amd", "csrc", "cg_sx_atomic.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "sx_stage_csr_n16777216_d32_counters.json")
+SX_SOURCES = [os.path.join(ROOT, "paper_1606_05732_amd", "csrc", f)
+              for f in ("cg_sx_binned.hip", "cg_rng.hpp", "cg_internal.hpp")]
+
+
+def sx_source_digest():
+    h = hashlib.sha256()
+    for f in SX_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -112,8 +125,7 @@ def counters_traffic(kernel_launches_bytes):
         return None
     with open(COUNTERS) as f:
         c = json.load(f)
-    src = hashlib.sha256(open(SX_SOURCE, "rb").read()).hexdigest()
-    if c.get("kernel_source_sha256") != src:
+    if c.get("kernel_source_sha256") != sx_source_digest():
         return None
     return c.get("traffic_bytes_per_launch")
 
@@ -166,6 +178,22 @@ def ladder(steps, warmup, ev):
     return out
 
 
+def copy_calibration(mib=512, reps=3):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters: run it under the same rocprofv3 --pmc pass as the
+    kernels, then bytes_true / counter_reading is the scale factor."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.randn(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4,
+                                           "launches": reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +202,8 @@ def main():
     ap.add_argument("--algo", default="auto", choices=["auto", "binned", "atomic", "sorted"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ladder", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -187,6 +217,9 @@ def main():
     from paper_1606_05732_amd import workloads as W
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_calibration:
+        copy_calibration()
+        return
     ev = HipEvents()
     log("generating workload ...")
     w = W.workload2()
@@ -221,7 +254,8 @@ def main():
         "config": {"workload": w.name, "n": c.n, "d": c.d, "density": 0.05, "nnz": nnz,
                    "m": w.m, "B": w.B, "values": "|N(0,1)| float32", "sx_algo": args.algo,
                    "precision": "fp32", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": f"S.X stage ({args.algo})",
+        "roofline": {"bound": "hbm",
+                     "kernel": f"S.X stage ({args.algo}: bin_count, bin_scan, bin_scatter, bin_reduce)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counters_traffic(sx_bytes),

@@ -8,16 +8,24 @@
 //
 //  1. split: the buckets are cut into R ranges of Bp = 2^k consecutive
 //     buckets whose S X slice fits in LDS.  bin_count counts every row
-//     tile's items per range; one exclusive scan over (range, tile) gives
-//     each tile a private window in each range's item list; bin_scatter_*
-//     fills the windows.  A scatter workgroup takes its tile in rounds of
-//     2048 rows: it counts the round's items per range, places them in LDS
-//     grouped by range, and writes each range's run with consecutive
-//     lanes on consecutive addresses (scattered 8-byte stores would cost
-//     partial-line writes to HBM).
+//     tile's items per range; bin_scan turns each range's per-tile counts
+//     into offsets inside the range and the range's total; the range
+//     bases are prefix sums of the totals, which each consumer forms
+//     itself.  That gives every tile a private window in each range's item
+//     list, which bin_scatter_* fills.  A scatter workgroup takes its tile
+//     in rounds of 1024 rows: it counts the round's items per range, places
+//     them in LDS grouped by range, and writes each range's run with
+//     consecutive lanes on consecutive addresses.
 //  2. reduce: one workgroup per range accumulates its items in LDS and
 //     writes the slice; every bucket of S X is written exactly once, so no
 //     zero fill is needed.
+//
+// Global loads are lane-contiguous everywhere: a wavefront reads the
+// row_ptr values of its 256 rows as one coalesced block and hands each lane
+// its four row starts through LDS, and a scatter round copies its whole
+// col_idx/vals segment into LDS with coalesced loads before any lane walks
+// its own rows.  (Lanes reading their own rows straight from memory touch
+// dozens of cache lines per load instruction and starve the address units.)
 //
 // CSR items are (cell = local bucket * d + column, sigma v).  They are
 // summed as 64-bit fixed-point integers with ds_add_u64: the range's scale
@@ -32,6 +40,11 @@
 // streams the rows of a contiguous group of buckets -- lanes across
 // columns, 16 rows in flight -- summing in registers, and adds a bucket's
 // sum into the LDS slice when the bucket changes.
+//
+// Malformed CSR input (decreasing row_ptr, row_ptr outside [0, nnz],
+// columns >= d) never causes an out-of-bounds access: row starts are
+// clamped, windows are bounded, columns out of range contribute nothing.
+// The result is then unspecified.
 #include "cg_internal.hpp"
 #include "cg_rng.hpp"
 
@@ -39,21 +52,36 @@ namespace cg {
 
 namespace {
 
-constexpr int kThreads = 1024;                 // count and reduce kernels
+constexpr int kThreads = 1024;                 // reduce kernels
 constexpr int kWaves = kThreads / 64;
-constexpr int kSThreads = 256;                 // scatter kernels: several per CU, so
-constexpr int kSWaves = kSThreads / 64;        // one's barriers overlap another's work
+constexpr int kSThreads = 256;                 // count, scan and scatter kernels
+constexpr int kSWaves = kSThreads / 64;
+constexpr int kRPT = 4;                        // rows per thread per round (4 per Philox block)
+constexpr int kWaveRows = kRPT * 64;           // rows per wavefront per round
+constexpr int kRoundRows = kRPT * kSThreads;   // rows per workgroup round
 constexpr int kTileRows = 16384;               // rows per split tile
-constexpr int kRPL = 8;                        // rows per lane per scatter round
-constexpr int kRoundRows = kRPL * kSThreads;   // rows per scatter round
-constexpr int kSegBatch = 16;                  // entries a lane loads at once
-constexpr size_t kScatterLds = 40 * 1024;      // LDS target of a scatter workgroup
+constexpr int kInCap = 2048;                   // CSR entries per LDS input chunk
+constexpr int kRpWin = kWaveRows + 4;          // LDS words of one row_ptr window
+constexpr size_t kScatterLds = 52 * 1024;      // LDS target of a scatter workgroup
+constexpr int kMinStage = 1024;                // smallest output stage (items)
 constexpr int kDenseCap = 8192;                // items sorted per dense reduce pass
+
+static_assert(kTileRows % kRoundRows == 0, "tiles hold whole rounds");
+static_assert(kInCap % kSThreads == 0, "input chunk is whole per-thread steps");
+static_assert(kRPT == 2 || kRPT % 4 == 0, "rows per thread: 2 or whole Philox blocks");
 
 extern __shared__ __align__(16) unsigned char dyn_lds[];
 
+// Orders LDS accesses of the lanes of one wavefront (their LDS operations
+// execute in program order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exclusive scan over the NT threads of the block; *total gets the sum.
-template <int NT = kThreads>
+template <int NT>
 __device__ uint32_t block_exscan(uint32_t v, uint32_t* s_w, uint32_t* total) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -81,90 +109,168 @@ __device__ uint32_t block_exscan(uint32_t v, uint32_t* s_w, uint32_t* total) {
   return before + x - v;
 }
 
+// ------------------------------------------------------------------ row_ptr
+// row_ptr of the wavefront's kWaveRows rows from r0 (kWaveRows + 1 values,
+// indices clamped to t1 so rows at or past t1 come out empty), read
+// lane-contiguous.
+struct RpLoad {
+  int32_t v[kRPT];
+  int32_t last;
+};
+
+__device__ __forceinline__ RpLoad load_row_ptr(const int32_t* __restrict__ row_ptr, int64_t r0,
+                                               int64_t t1) {
+  const int lane = threadIdx.x & 63;
+  RpLoad l;
+#pragma unroll
+  for (int j = 0; j < kRPT; ++j) l.v[j] = row_ptr[min(r0 + lane + 64 * j, t1)];
+  l.last = row_ptr[min(r0 + kWaveRows, t1)];
+  return l;
+}
+
+// Hands lane l the row starts rp[0 .. kRPT] of rows r0 + kRPT l + j through
+// the wavefront's LDS window w (kRpWin words).  Values are clamped to
+// [0, nnz] and made non-decreasing, so row lengths are never negative.
+__device__ __forceinline__ void transpose_row_ptr(const RpLoad& l, int32_t* w, int32_t nnz,
+                                                  int32_t rp[kRPT + 1]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < kRPT; ++j) w[lane + 64 * j] = l.v[j];
+  if (lane == 0) w[kWaveRows] = l.last;
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j <= kRPT; ++j) rp[j] = min(max(w[kRPT * lane + j], 0), nnz);
+#pragma unroll
+  for (int j = 1; j <= kRPT; ++j) rp[j] = max(rp[j], rp[j - 1]);
+  wave_sync();
+}
+
+// Packed hashes of this lane's kRPT rows r .. r + kRPT - 1 (zero past t1).
+__device__ __forceinline__ void lane_hashes(int64_t r, int64_t t1, uint64_t row_offset, uint32_t B,
+                                            Key key, uint32_t hv[kRPT]) {
+#pragma unroll
+  for (int g = 0; g < kRPT; g += 4) {
+    uint32_t h4[4] = {0u, 0u, 0u, 0u};
+    if (r + g < t1) hash4(row_offset + (uint64_t)(r + g), B, key.k0, key.k1, h4);
+#pragma unroll
+    for (int t = 0; t < 4 && g + t < kRPT; ++t) hv[g + t] = h4[t];
+  }
+}
+
 // ------------------------------------------------------------------ count
+// hist[p * ntiles + t] = items of tile t that fall in range p.  Two rounds
+// per iteration, so each wavefront has ten row_ptr loads in flight.
 template <bool CSR>
-__global__ __launch_bounds__(kThreads) void bin_count_kernel(
+__global__ __launch_bounds__(kSThreads) void bin_count_kernel(
     const int32_t* __restrict__ row_ptr, int64_t n, int32_t nnz, uint32_t B, Key key,
     uint64_t row_offset, int bp_shift, int R, int64_t ntiles, uint32_t* __restrict__ hist) {
   uint32_t* s_cnt = (uint32_t*)dyn_lds;
-  for (int i = threadIdx.x; i < R; i += kThreads) s_cnt[i] = 0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int32_t* w = (int32_t*)(s_cnt + R) + wave * 2 * kRpWin;
+  for (int i = threadIdx.x; i < R; i += kSThreads) s_cnt[i] = 0;
   __syncthreads();
   const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
   const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
-  // four rows per thread per step, four steps per batch; every step's
-  // row_ptr loads go out before any is used.  (Indices are clamped instead
-  // of guarded: a guarded load becomes a branch with its own wait.)
-  constexpr int S = 4;
-  for (int64_t b0 = t0; b0 < t1; b0 += (int64_t)S * 4 * kThreads) {
-    int32_t ptr[S][5];
+  for (int64_t round = t0; round < t1; round += 2 * kRoundRows) {
+    const int64_t ra = round + (int64_t)kWaveRows * wave, rb = ra + kRoundRows;
+    RpLoad la, lb;
     if (CSR) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int64_t r = b0 + 4 * ((int64_t)s * kThreads + threadIdx.x);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) ptr[s][j] = row_ptr[min(r + j, t1)];
-      }
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int j = 0; j < 5; ++j) ptr[s][j] = min(max(ptr[s][j], 0), nnz);
+      la = load_row_ptr(row_ptr, ra, t1);
+      lb = load_row_ptr(row_ptr, rb, t1);
     }
+    uint32_t ha[kRPT], hb[kRPT];
+    lane_hashes(ra + kRPT * lane, t1, row_offset, B, key, ha);
+    lane_hashes(rb + kRPT * lane, t1, row_offset, B, key, hb);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int64_t r = b0 + 4 * ((int64_t)s * kThreads + threadIdx.x);
-      if (r >= t1) continue;
-      uint32_t hv[4];
-      hash4(row_offset + (uint64_t)r, B, key.k0, key.k1, hv);
+    for (int half = 0; half < 2; ++half) {
+      const int64_t r = (half ? rb : ra) + kRPT * lane;
+      const uint32_t* hv = half ? hb : ha;
+      int32_t rp[kRPT + 1];
+      if (CSR) transpose_row_ptr(half ? lb : la, w + half * kRpWin, nnz, rp);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (r + j < t1) {
-          const uint32_t len = CSR ? (uint32_t)max(ptr[s][j + 1] - ptr[s][j], 0) : 1u;
-          if (len) atomicAdd(&s_cnt[hash_bucket(hv[j]) >> bp_shift], len);
-        }
+      for (int j = 0; j < kRPT; ++j) {
+        const uint32_t len = CSR ? (uint32_t)(rp[j + 1] - rp[j]) : (r + j < t1 ? 1u : 0u);
+        if (len) atomicAdd(&s_cnt[hash_bucket(hv[j]) >> bp_shift], len);
       }
     }
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < R; p += kThreads) hist[(int64_t)p * ntiles + blockIdx.x] = s_cnt[p];
+  for (int p = threadIdx.x; p < R; p += kSThreads) hist[(int64_t)p * ntiles + blockIdx.x] = s_cnt[p];
 }
 
-// Per-range base offset of this tile's window and its end (never past the
-// item buffer, even if a malformed CSR made the counts exceed nnz).
-__device__ __forceinline__ void load_windows(const uint32_t* __restrict__ offs, int R,
-                                             int64_t ntiles, uint32_t total, uint32_t* g_base,
-                                             uint32_t* g_next) {
-  const int64_t len = (int64_t)R * ntiles;
-  for (int p = threadIdx.x; p < R; p += kSThreads) {
-    const int64_t idx = (int64_t)p * ntiles + blockIdx.x;
-    g_base[p] = offs[idx];
-    g_next[p] = min(idx + 1 < len ? offs[idx + 1] : total, total);
+// ------------------------------------------------------------------ scan
+// Workgroup p: hist[p][0 .. ntiles) becomes its exclusive prefix sums and
+// tot[p] the range's item count.
+__global__ __launch_bounds__(kSThreads) void bin_scan_kernel(uint32_t* __restrict__ hist,
+                                                             int64_t ntiles,
+                                                             uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_w[kSWaves];
+  uint32_t* h = hist + (int64_t)blockIdx.x * ntiles;
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += 4 * kSThreads) {
+    const int64_t i = c0 + 4 * (int64_t)threadIdx.x;
+    uint32_t v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = h[min(i + j, ntiles - 1)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (i + j >= ntiles) v[j] = 0u;
+    uint32_t all;
+    uint32_t run = carry + block_exscan<kSThreads>(v[0] + v[1] + v[2] + v[3], s_w, &all);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (i + j < ntiles) h[i + j] = run;
+      run += v[j];
+    }
+    carry += all;
   }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-// LDS of the scatter kernels: stage | per-range arrays | block scan.
+// ------------------------------------------------------------------ scatter
+// LDS of the scatter kernels:
+//   stage (cap items) | input chunk (kInCap items) sharing its space with
+//   the row_ptr windows (CSR only; a round uses the windows first, then
+//   the chunk) | per-range arrays (7 R words) | block scan | segment
 struct ScatterLds {
   uint2* stage;
+  uint2* in;
+  int32_t* rpw;     // kSWaves windows of kRpWin words, aliasing `in`
   uint32_t *g_base, *g_next, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
+  uint2* fl;        // R: (window slot of stage index 0, window end) for the flush
   uint32_t* s_w;    // kSWaves
+  int32_t* s_seg;   // 2
 };
 
-// Items a scatter round may stage: what is left of the LDS target after
-// the per-range arrays (at least one round of dense rows).
-__host__ __device__ inline int stage_cap(int R) {
-  const int64_t left = (int64_t)kScatterLds - (int64_t)7 * R * 4 - kSWaves * 4;
-  int cap = (int)((left > 0 ? left : 0) / 8) & ~255;
-  return cap < kRoundRows ? kRoundRows : cap;
+__host__ __device__ inline size_t scatter_shared_bytes(bool csr) {
+  const size_t in = (size_t)kInCap * 8, win = (size_t)kSWaves * kRpWin * 4;
+  return csr ? (in > win ? in : win) : 0;
 }
 
-__host__ __device__ inline size_t scatter_lds_bytes(int R) {
-  return (size_t)stage_cap(R) * 8 + (size_t)7 * R * 4 + kSWaves * 4;
+__host__ __device__ inline size_t scatter_fixed_bytes(int R, bool csr) {
+  return scatter_shared_bytes(csr) + (size_t)9 * R * 4 + kSWaves * 4 + 8;
 }
 
-__device__ __forceinline__ ScatterLds carve_scatter(int R) {
+// Items a scatter round may stage: what the LDS target leaves after the
+// fixed arrays, at least kMinStage.
+__host__ __device__ inline int stage_cap(int R, bool csr) {
+  const int64_t left = (int64_t)kScatterLds - (int64_t)scatter_fixed_bytes(R, csr);
+  const int cap = (int)((left > 0 ? left : 0) / 8) & ~255;
+  return cap < kMinStage ? kMinStage : cap;
+}
+
+__host__ __device__ inline size_t scatter_lds_bytes(int R, bool csr) {
+  return (size_t)stage_cap(R, csr) * 8 + scatter_fixed_bytes(R, csr);
+}
+
+__device__ __forceinline__ ScatterLds carve_scatter(int R, bool csr) {
   ScatterLds L;
   unsigned char* p = dyn_lds;
   L.stage = (uint2*)p;
-  p += (size_t)stage_cap(R) * 8;
+  p += (size_t)stage_cap(R, csr) * 8;
+  L.in = (uint2*)p;
+  L.rpw = (int32_t*)p;
+  p += scatter_shared_bytes(csr);
   uint32_t* q = (uint32_t*)p;
   L.g_base = q;
   L.g_next = q + R;
@@ -173,16 +279,40 @@ __device__ __forceinline__ ScatterLds carve_scatter(int R) {
   L.r_off = q + 4 * R;
   L.r_fill = q + 5 * R;
   L.r_max = q + 6 * R;
-  L.s_w = q + 7 * R;
+  L.fl = (uint2*)(q + 7 * R);
+  L.s_w = q + 9 * R;
+  L.s_seg = (int32_t*)(L.s_w + kSWaves);
   return L;
 }
 
-__device__ __forceinline__ void clear_ranges(const ScatterLds& L, int R) {
-  for (int p = threadIdx.x; p < R; p += kSThreads) {
+// This tile's window [g_base, g_next) in every range's item list: range
+// bases are the prefix sums of the range totals, plus the tile's offset
+// inside the range (never past the item buffer, even if a malformed CSR
+// made the counts exceed nnz).  Also clears the per-range round state.
+__device__ __forceinline__ void load_windows(const ScatterLds& L, const uint32_t* __restrict__ offs,
+                                             const uint32_t* __restrict__ tot, int R,
+                                             int64_t ntiles, uint32_t total) {
+  const int per = (R + kSThreads - 1) / kSThreads;
+  const int b = (int)threadIdx.x * per;
+  uint32_t local = 0;
+  for (int k = 0; k < per; ++k)
+    if (b + k < R) local += tot[b + k];
+  uint32_t all;
+  uint64_t base = block_exscan<kSThreads>(local, L.s_w, &all);
+  const int64_t t = blockIdx.x;
+  for (int k = 0; k < per; ++k) {
+    const int p = b + k;
+    if (p >= R) break;
+    const uint32_t tp = tot[p];
+    const uint64_t lo = base + offs[(int64_t)p * ntiles + t];
+    const uint64_t hi = base + (t + 1 < ntiles ? offs[(int64_t)p * ntiles + t + 1] : tp);
+    L.g_base[p] = (uint32_t)min(lo, (uint64_t)total);
+    L.g_next[p] = (uint32_t)min(hi, (uint64_t)total);
     L.g_run[p] = 0;
     L.r_cnt[p] = 0;
     L.r_fill[p] = 0;
     L.r_max[p] = 0;
+    base += tp;
   }
 }
 
@@ -197,9 +327,11 @@ __device__ __forceinline__ uint32_t round_offsets(const ScatterLds& L, int R) {
   uint32_t E;
   uint32_t run = block_exscan<kSThreads>(local, L.s_w, &E);
   for (int k = 0; k < per; ++k) {
-    if (b + k < R) {
-      L.r_off[b + k] = run;
-      run += L.r_cnt[b + k];
+    const int p = b + k;
+    if (p < R) {
+      L.r_off[p] = run;
+      L.fl[p] = make_uint2(L.g_base[p] + L.g_run[p] - run, L.g_next[p]);
+      run += L.r_cnt[p];
     }
   }
   __syncthreads();
@@ -215,8 +347,10 @@ __device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t
   for (uint32_t i = threadIdx.x; i < E; i += kSThreads) {
     const uint2 it = L.stage[i];
     const uint32_t p = it.x >> 16;
-    const uint32_t pos = L.g_base[p] + L.g_run[p] + (i - L.r_off[p]);
-    if (pos < L.g_next[p])
+    if (p >= (uint32_t)R) continue;   // a slot no item filled (malformed CSR)
+    const uint2 f = L.fl[p];
+    const uint32_t pos = i + f.x;
+    if (pos < f.y)
       items[pos] = swap ? make_uint2(it.y, it.x & 0xffffu) : make_uint2(it.x & 0xffffu, it.y);
   }
   __syncthreads();
@@ -227,111 +361,107 @@ __device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t
   }
 }
 
-// ------------------------------------------------------------------ scatter (CSR)
-// A round takes 2048 rows, eight consecutive rows per lane, whose entries
-// form one contiguous segment of col_idx/vals.  A lane loads its segment in
-// batches of 16 entries (all loads of a batch in flight together), finds
-// each entry's row by comparing with the row starts, and reserves slots per
-// row, not per entry.
+// CSR.  A round is 1024 rows, four consecutive rows per lane.  The lanes
+// count their rows' entries per range and reserve slots per row; the
+// round's entries -- one contiguous segment of col_idx/vals -- are copied
+// into LDS in chunks of kInCap with coalesced loads, and every lane then
+// walks its own rows' entries there and stages the items.
 __global__ __launch_bounds__(kSThreads) void bin_scatter_csr_kernel(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ vals, int64_t n, int32_t nnz, int d, uint32_t B, Key key,
     uint64_t row_offset, int bp_shift, int R, int64_t ntiles, const uint32_t* __restrict__ offs,
-    uint32_t total, uint2* __restrict__ items, uint32_t* __restrict__ hmax) {
-  const ScatterLds L = carve_scatter(R);
-  const uint32_t cap = (uint32_t)stage_cap(R);
-  load_windows(offs, R, ntiles, total, L.g_base, L.g_next);
-  clear_ranges(L, R);
+    const uint32_t* __restrict__ tot, uint32_t total, uint2* __restrict__ items,
+    uint32_t* __restrict__ hmax) {
+  const ScatterLds L = carve_scatter(R, true);
+  const uint32_t cap = (uint32_t)stage_cap(R, true);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int32_t* w = L.rpw + wave * kRpWin;
+  load_windows(L, offs, tot, R, ntiles, total);
   const uint32_t bmask = (1u << bp_shift) - 1u;
   const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
   const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
   for (int64_t round = t0; round < t1; round += kRoundRows) {
-    __syncthreads();
-    const int64_t r = round + (int64_t)kRPL * threadIdx.x;
-    int32_t rp[kRPL + 1];
+    const int64_t r0 = round + (int64_t)kWaveRows * wave;
+    const RpLoad rl = load_row_ptr(row_ptr, r0, t1);
+    uint32_t hv[kRPT];
+    lane_hashes(r0 + kRPT * lane, t1, row_offset, B, key, hv);
+    __syncthreads();   // the previous round's flush is done with the LDS state
+    int32_t rp[kRPT + 1];
+    transpose_row_ptr(rl, w, nnz, rp);
+    uint32_t len[kRPT];
 #pragma unroll
-    for (int j = 0; j <= kRPL; ++j) rp[j] = row_ptr[min(r + j, t1)];
-#pragma unroll
-    for (int j = 0; j <= kRPL; ++j) rp[j] = min(max(rp[j], 0), nnz);
-#pragma unroll
-    for (int j = 1; j <= kRPL; ++j) rp[j] = max(rp[j], rp[j - 1]);   // malformed rows -> empty
-    uint32_t hv[kRPL];
-#pragma unroll
-    for (int j = 0; j < kRPL; j += 4) {
-      uint32_t h4[4] = {0u, 0u, 0u, 0u};
-      if (r + j < t1) hash4(row_offset + (uint64_t)(r + j), B, key.k0, key.k1, h4);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) hv[j + t] = h4[t];
-    }
-    uint32_t len[kRPL];
-#pragma unroll
-    for (int j = 0; j < kRPL; ++j) {
+    for (int j = 0; j < kRPT; ++j) {
       len[j] = (uint32_t)(rp[j + 1] - rp[j]);   // zero for rows at or past t1
       if (len[j]) atomicAdd(&L.r_cnt[hash_bucket(hv[j]) >> bp_shift], len[j]);
     }
+    if (threadIdx.x == 0) L.s_seg[0] = rp[0];
+    if (threadIdx.x == kSThreads - 1) L.s_seg[1] = rp[kRPT];
     __syncthreads();
     const uint32_t E = round_offsets(L, R);
     const bool staged = E <= cap;
-    // per row: first slot of its entries (stage index, or window index)
-    uint32_t slot0[kRPL], maxb[kRPL];
+    // slot of entry k of row j: sadj[j] + k (mod 2^32)
+    uint32_t sadj[kRPT], maxb[kRPT];
 #pragma unroll
-    for (int j = 0; j < kRPL; ++j) {
+    for (int j = 0; j < kRPT; ++j) {
       const uint32_t p = hash_bucket(hv[j]) >> bp_shift;
       const uint32_t b = len[j] ? atomicAdd(&L.r_fill[p], len[j]) : 0u;
-      slot0[j] = staged ? L.r_off[p] + b : L.g_base[p] + L.g_run[p] + b;
+      const uint32_t s0 = staged ? L.r_off[p] + b : L.g_base[p] + L.g_run[p] + b;
+      sadj[j] = s0 - (uint32_t)rp[j];
       maxb[j] = 0u;
     }
-    const int32_t seg0 = rp[0], seg1 = rp[kRPL];
-    int32_t span = seg1 - seg0;
+    const int32_t S0 = L.s_seg[0];
+    const int32_t S1 = max(L.s_seg[1], S0);
+    for (int32_t c0 = S0; c0 < S1; c0 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1)) {
+      const int32_t c1 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1);
+      if (c0 != S0) __syncthreads();   // every lane is done with the previous chunk
+      int32_t cc[kInCap / kSThreads];
+      float vv[kInCap / kSThreads];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) span = max(span, __shfl_xor(span, off, 64));
-    for (int32_t t = 0; t < span; t += kSegBatch) {
-      int32_t cc[kSegBatch];
-      float vv[kSegBatch];
-      // span > 0, so nnz >= 1 and the clamped index is always readable
-#pragma unroll
-      for (int u = 0; u < kSegBatch; ++u) {
-        const int32_t k = seg1 > seg0 ? min(seg0 + t + u, seg1 - 1) : 0;
+      for (int u = 0; u < kInCap / kSThreads; ++u) {
+        const int32_t k = min(c0 + (int32_t)threadIdx.x + u * kSThreads, c1 - 1);
         cc[u] = col_idx[k];
         vv[u] = vals[k];
       }
 #pragma unroll
-      for (int u = 0; u < kSegBatch; ++u) {
-        const int32_t k = seg0 + t + u;
-        if (k >= seg1) break;
+      for (int u = 0; u < kInCap / kSThreads; ++u) {
+        const int32_t i = (int32_t)threadIdx.x + u * kSThreads;
+        if (i < c1 - c0) L.in[i] = make_uint2((uint32_t)cc[u], __float_as_uint(vv[u]));
+      }
+      __syncthreads();
+      const int32_t a = max(rp[0], c0), e = min(rp[kRPT], c1);
+      for (int32_t k = a; k < e; ++k) {
         int j = 0;
 #pragma unroll
-        for (int q = 1; q < kRPL; ++q) j += k >= rp[q];
-        uint32_t hj = hv[0], sj = slot0[0];
-        int32_t rs = rp[0];
+        for (int q = 1; q < kRPT; ++q) j += k >= rp[q];
+        uint32_t hj = hv[0], sj = sadj[0];
 #pragma unroll
-        for (int q = 1; q < kRPL; ++q)
+        for (int q = 1; q < kRPT; ++q)
           if (j == q) {
             hj = hv[q];
-            sj = slot0[q];
-            rs = rp[q];
+            sj = sadj[q];
           }
+        const uint2 in = L.in[k - c0];
         const uint32_t bucket = hash_bucket(hj);
         const uint32_t p = bucket >> bp_shift;
-        const int32_t c = cc[u];
-        const bool ok = (unsigned)c < (unsigned)d;
-        const uint32_t cell = ok ? (bucket & bmask) * (uint32_t)d + (uint32_t)c : 0u;
-        const float sv = ok ? (hash_negative(hj) ? -vv[u] : vv[u]) : 0.0f;
-        const uint32_t slot = sj + (uint32_t)(k - rs);
+        const bool ok = in.x < (uint32_t)d;
+        const float v = __uint_as_float(in.y);
+        const uint32_t cell = ok ? (bucket & bmask) * (uint32_t)d + in.x : 0u;
+        const float sv = ok ? (hash_negative(hj) ? -v : v) : 0.0f;
+        const uint32_t slot = sj + (uint32_t)k;
         const uint32_t mb = __float_as_uint(fabsf(sv));
 #pragma unroll
-        for (int q = 0; q < kRPL; ++q)
+        for (int q = 0; q < kRPT; ++q)
           if (j == q) maxb[q] = max(maxb[q], mb);
         if (staged) {
           if (slot < E) L.stage[slot] = make_uint2((p << 16) | cell, __float_as_uint(sv));
         } else {
-          // a round too large for the stage (very long rows): direct stores
+          // a round too large for the stage (long rows): direct stores
           if (slot < L.g_next[p]) items[slot] = make_uint2(cell, __float_as_uint(sv));
         }
       }
     }
 #pragma unroll
-    for (int j = 0; j < kRPL; ++j)
+    for (int j = 0; j < kRPT; ++j)
       if (len[j]) atomicMax(&L.r_max[hash_bucket(hv[j]) >> bp_shift], maxb[j]);
     __syncthreads();
     flush_stage(L, R, staged ? E : 0u, false, items);
@@ -340,35 +470,28 @@ __global__ __launch_bounds__(kSThreads) void bin_scatter_csr_kernel(
   for (int q = threadIdx.x; q < R; q += kSThreads) hmax[(int64_t)q * ntiles + blockIdx.x] = L.r_max[q];
 }
 
-// ------------------------------------------------------------------ scatter (dense)
+// Dense.  A round is 1024 rows, four per lane, one item per row.
 __global__ __launch_bounds__(kSThreads) void bin_scatter_dense_kernel(
     int64_t n, uint32_t B, Key key, uint64_t row_offset, int bp_shift, int R, int64_t ntiles,
-    const uint32_t* __restrict__ offs, uint32_t total, uint2* __restrict__ items) {
-  const ScatterLds L = carve_scatter(R);
-  load_windows(offs, R, ntiles, total, L.g_base, L.g_next);
-  clear_ranges(L, R);
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ tot, uint32_t total,
+    uint2* __restrict__ items) {
+  const ScatterLds L = carve_scatter(R, false);
+  load_windows(L, offs, tot, R, ntiles, total);
   const uint32_t bmask = (1u << bp_shift) - 1u;
   const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
   const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
-  // rounds of kRoundRows rows: one item per row, within the stage capacity
   for (int64_t round = t0; round < t1; round += kRoundRows) {
+    const int64_t r = round + (int64_t)kRPT * threadIdx.x;
+    uint32_t hv[kRPT];
+    lane_hashes(r, t1, row_offset, B, key, hv);
     __syncthreads();
-    const int64_t r = round + (int64_t)kRPL * threadIdx.x;
-    uint32_t hv[kRPL];
 #pragma unroll
-    for (int j = 0; j < kRPL; j += 4) {
-      uint32_t h4[4] = {0u, 0u, 0u, 0u};
-      if (r + j < t1) hash4(row_offset + (uint64_t)(r + j), B, key.k0, key.k1, h4);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) hv[j + t] = h4[t];
-    }
-#pragma unroll
-    for (int j = 0; j < kRPL; ++j)
+    for (int j = 0; j < kRPT; ++j)
       if (r + j < t1) atomicAdd(&L.r_cnt[hash_bucket(hv[j]) >> bp_shift], 1u);
     __syncthreads();
     const uint32_t E = round_offsets(L, R);   // <= kRoundRows <= stage capacity
 #pragma unroll
-    for (int j = 0; j < kRPL; ++j) {
+    for (int j = 0; j < kRPT; ++j) {
       if (r + j < t1) {
         const uint32_t bucket = hash_bucket(hv[j]);
         const uint32_t p = bucket >> bp_shift;
@@ -396,21 +519,36 @@ __device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* s_red) {
   return r;
 }
 
-__device__ __forceinline__ void range_of(const uint32_t* __restrict__ offs, int p, int R,
-                                         int64_t ntiles, uint32_t total, uint32_t* start,
-                                         uint32_t* end) {
-  const uint32_t s = offs[(int64_t)p * ntiles];
-  const uint32_t e = p + 1 < R ? offs[(int64_t)(p + 1) * ntiles] : total;
-  *start = min(s, total);
-  *end = min(max(e, *start), total);
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s_red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t r = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) r += s_red[w];
+  __syncthreads();
+  return r;
+}
+
+// Items of range p: [sum of tot[0 .. p), + tot[p]), clamped to the buffer.
+__device__ __forceinline__ void range_of(const uint32_t* __restrict__ tot, int p, uint32_t total,
+                                         uint64_t* s_red, uint32_t* start, uint32_t* end) {
+  uint64_t s = 0;
+  for (int q = threadIdx.x; q < p; q += kThreads) s += tot[q];
+  s = block_sum_u64(s, s_red);
+  const uint64_t e = s + tot[p];
+  *start = (uint32_t)min(s, (uint64_t)total);
+  *end = (uint32_t)min(max(e, (uint64_t)*start), (uint64_t)total);
 }
 
 __global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(
-    const uint2* __restrict__ items, const uint32_t* __restrict__ offs,
-    const uint32_t* __restrict__ hmax, int64_t ntiles, int R, uint32_t total, uint32_t B, int d,
+    const uint2* __restrict__ items, const uint32_t* __restrict__ tot,
+    const uint32_t* __restrict__ hmax, int64_t ntiles, uint32_t total, uint32_t B, int d,
     int bp_shift, float* __restrict__ SX) {
   unsigned long long* s_acc = (unsigned long long*)dyn_lds;
   __shared__ uint32_t s_red[kWaves];
+  __shared__ uint64_t s_red64[kWaves];
   const int p = blockIdx.x;
   const int cells = (1 << bp_shift) * d;
   for (int i = threadIdx.x; i < cells; i += kThreads) s_acc[i] = 0ull;
@@ -418,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(
   for (int64_t t = threadIdx.x; t < ntiles; t += kThreads) mx = max(mx, hmax[(int64_t)p * ntiles + t]);
   const uint32_t amax_bits = block_max_u32(mx, s_red);   // its barrier also orders the zero fill
   uint32_t start, end;
-  range_of(offs, p, R, ntiles, total, &start, &end);
+  range_of(tot, p, total, s_red64, &start, &end);
   if (amax_bits >= 0x7f800000u) {
     // a NaN or an infinity in this range: float atomics keep IEEE semantics
     float* acc = (float*)s_acc;
@@ -476,11 +614,12 @@ __host__ __device__ inline size_t dense_reduce_lds_bytes(int Bp, int d) {
 template <int LPR>
 __global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t n, const uint2* __restrict__ items,
-    const uint32_t* __restrict__ offs, int64_t ntiles, int R, uint32_t total, uint32_t B, int d,
-    int bp_shift, float* __restrict__ SX) {
+    const uint32_t* __restrict__ tot, uint32_t total, uint32_t B, int d, int bp_shift,
+    float* __restrict__ SX) {
   constexpr int RPP = 64 / LPR;                // rows per instruction (one per lane group)
   constexpr int U = RPP >= 8 ? 4 : 16 / RPP;   // row loads in flight per lane group
   constexpr int PER = kDenseCap / kThreads;    // items held per thread
+  __shared__ uint64_t s_red64[kWaves];
   const int Bp = 1 << bp_shift;
   const int cells = Bp * d;
   float* slice = (float*)dyn_lds;
@@ -499,7 +638,7 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(
   const int lb0 = (int)(((int64_t)Bp * wave) / kWaves), lb1 = (int)(((int64_t)Bp * (wave + 1)) / kWaves);
   for (int i = threadIdx.x; i < cells; i += kThreads) slice[i] = 0.0f;
   uint32_t start, end;
-  range_of(offs, p, R, ntiles, total, &start, &end);
+  range_of(tot, p, total, s_red64, &start, &end);
   for (uint32_t c0 = start; c0 < end; c0 += kDenseCap) {
     const uint32_t nit = min(end - c0, (uint32_t)kDenseCap);
     for (int b = threadIdx.x; b < Bp; b += kThreads) {
@@ -519,8 +658,9 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(
     }
     __syncthreads();
     // exclusive scan of the bucket counts (Bp <= 1024: one per thread)
-    uint32_t tot;
-    const uint32_t ex = block_exscan(threadIdx.x < (unsigned)Bp ? cnt[threadIdx.x] : 0u, s_w, &tot);
+    uint32_t tt;
+    const uint32_t ex =
+        block_exscan<kThreads>(threadIdx.x < (unsigned)Bp ? cnt[threadIdx.x] : 0u, s_w, &tt);
     if (threadIdx.x < (unsigned)Bp) off[threadIdx.x] = ex;
     __syncthreads();
 #pragma unroll
@@ -538,7 +678,7 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(
     // lane group j taking every RPP-th row, U rows in flight; a running sum
     // per lane is added into the slice whenever the bucket changes
     const uint32_t s = lb0 < Bp ? off[lb0] : 0u;
-    const uint32_t e = lb1 < Bp ? off[lb1] : min(tot, (uint32_t)kDenseCap);
+    const uint32_t e = lb1 < Bp ? off[lb1] : min(tt, (uint32_t)kDenseCap);
     float acc = 0.0f;
     int cur = -1;
     for (uint32_t i = s + j; i < max(e, s + j); i += RPP * U) {
@@ -580,8 +720,9 @@ int lanes_per_row(int d) {
   return l;
 }
 
+// Scratch: hist (R x ntiles) | tot (R) | hmax (R x ntiles) | items
 struct Carve {
-  uint32_t *hist, *sums, *hmax;
+  uint32_t *hist, *tot, *hmax;
   uint2* items;
 };
 
@@ -591,8 +732,8 @@ Carve carve(void* base, const BinGeom& g) {
   const int64_t hl = (int64_t)g.R * g.ntiles;
   c.hist = (uint32_t*)p;
   p += align256((size_t)hl * 4);
-  c.sums = (uint32_t*)p;
-  p += align256((size_t)scan_sums_len(hl) * 4);
+  c.tot = (uint32_t*)p;
+  p += align256((size_t)g.R * 4);
   c.hmax = (uint32_t*)p;
   p += align256((size_t)hl * 4);
   c.items = (uint2*)p;
@@ -606,6 +747,8 @@ hipError_t allow_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)bytes);
 }
+
+size_t count_lds_bytes(int R) { return (size_t)R * 4 + (size_t)kSWaves * 2 * kRpWin * 4; }
 
 }  // namespace
 
@@ -624,14 +767,13 @@ BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B) {
   g.ntiles = (n + kTileRows - 1) / kTileRows;
   g.ok = g.R <= (csr ? kBinMaxRangesCsr : kBinMaxRangesDense) && d <= (csr ? kMaxD : 64) &&
          n < ((int64_t)1 << 31) && (int64_t)g.R * g.ntiles < ((int64_t)1 << 30) &&
-         scatter_lds_bytes(g.R) <= 96 * 1024;
+         scatter_lds_bytes(g.R, csr) <= 160 * 1024 && stage_cap(g.R, csr) >= kRoundRows;
   return g;
 }
 
 size_t binned_scratch_bytes(const BinGeom& g, int64_t count) {
   const int64_t hl = (int64_t)g.R * g.ntiles;
-  return 2 * align256((size_t)hl * 4) + align256((size_t)scan_sums_len(hl) * 4) +
-         align256((size_t)count * 8);
+  return 2 * align256((size_t)hl * 4) + align256((size_t)g.R * 4) + align256((size_t)count * 8);
 }
 
 hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
@@ -640,20 +782,20 @@ hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, 
                                 void* const* events) {
   const BinGeom g = bin_geometry(true, n, d, B);
   Carve c = carve(scratch, g);
-  const int64_t hl = (int64_t)g.R * g.ntiles;
-  const size_t sl = scatter_lds_bytes(g.R);
+  const size_t sl = scatter_lds_bytes(g.R, true), cl = count_lds_bytes(g.R);
   hipError_t e;
+  if ((e = allow_lds(bin_count_kernel<true>, cl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_scatter_csr_kernel, sl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_reduce_csr_kernel, g.lds_bytes)) != hipSuccess) return e;
-  bin_count_kernel<true><<<(unsigned)g.ntiles, kThreads, g.R * 4, s>>>(
+  bin_count_kernel<true><<<(unsigned)g.ntiles, kSThreads, cl, s>>>(
       row_ptr, n, (int32_t)nnz, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist);
-  if ((e = launch_exclusive_scan(c.hist, hl, c.sums, s)) != hipSuccess) return e;
+  bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(c.hist, g.ntiles, c.tot);
   if (events && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
   bin_scatter_csr_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(
       row_ptr, col_idx, vals, n, (int32_t)nnz, d, B, key, row_offset, g.bp_shift, g.R, g.ntiles,
-      c.hist, (uint32_t)nnz, c.items, c.hmax);
+      c.hist, c.tot, (uint32_t)nnz, c.items, c.hmax);
   bin_reduce_csr_kernel<<<(unsigned)g.R, kThreads, g.lds_bytes, s>>>(
-      c.items, c.hist, c.hmax, g.ntiles, g.R, (uint32_t)nnz, B, d, g.bp_shift, SX);
+      c.items, c.tot, c.hmax, g.ntiles, (uint32_t)nnz, B, d, g.bp_shift, SX);
   return hipGetLastError();
 }
 
@@ -662,22 +804,22 @@ hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d,
                                   hipStream_t s, void* const* events) {
   const BinGeom g = bin_geometry(false, n, d, B);
   Carve c = carve(scratch, g);
-  const int64_t hl = (int64_t)g.R * g.ntiles;
-  const size_t sl = scatter_lds_bytes(g.R);
+  const size_t sl = scatter_lds_bytes(g.R, false), cl = count_lds_bytes(g.R);
   hipError_t e;
+  if ((e = allow_lds(bin_count_kernel<false>, cl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_scatter_dense_kernel, sl)) != hipSuccess) return e;
-  bin_count_kernel<false><<<(unsigned)g.ntiles, kThreads, g.R * 4, s>>>(
+  bin_count_kernel<false><<<(unsigned)g.ntiles, kSThreads, cl, s>>>(
       nullptr, n, 0, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist);
-  if ((e = launch_exclusive_scan(c.hist, hl, c.sums, s)) != hipSuccess) return e;
+  bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(c.hist, g.ntiles, c.tot);
   if (events && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
   bin_scatter_dense_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(
-      n, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist, (uint32_t)n, c.items);
+      n, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist, c.tot, (uint32_t)n, c.items);
   const unsigned gr = (unsigned)g.R;
   const size_t rl = g.lds_bytes;
-#define CG_DENSE_REDUCE(L)                                                                       \
-  if ((e = allow_lds(bin_reduce_dense_kernel<L>, rl)) != hipSuccess) return e;                   \
-  bin_reduce_dense_kernel<L><<<gr, kThreads, rl, s>>>(X, ldx, n, c.items, c.hist, g.ntiles, g.R, \
-                                                      (uint32_t)n, B, d, g.bp_shift, SX);
+#define CG_DENSE_REDUCE(L)                                                                     \
+  if ((e = allow_lds(bin_reduce_dense_kernel<L>, rl)) != hipSuccess) return e;                 \
+  bin_reduce_dense_kernel<L><<<gr, kThreads, rl, s>>>(X, ldx, n, c.items, c.tot, (uint32_t)n, \
+                                                      B, d, g.bp_shift, SX);
   switch (lanes_per_row(d)) {
     case 1: CG_DENSE_REDUCE(1) break;
     case 2: CG_DENSE_REDUCE(2) break;
