@@ -20,6 +20,8 @@ Prints ONE JSON line on stdout (everything else goes to stderr):
   ladder       the G.(S X) precision ladder on the dense spiky workload
                (n = 2^22, d = 64, m = 64, B = 262144): time per step and
                error against the FP64 oracle for FP32, BF16 and FP8 inputs
+  batched      512 uneven CSR instances: 512 sequential calls against one
+               batch (built-in tuning table, then autotuned)
 """
 import argparse
 import ctypes
@@ -178,6 +180,56 @@ def ladder(steps, warmup, ev):
     return out
 
 
+def batched(log_fn):
+    """The batched workload (512 uneven CSR instances, m = 32): 512
+    sequential single-instance calls against one batch, with the built-in
+    tuning table and after the autotuner."""
+    import torch
+
+    import paper_1606_05732_amd as cg
+    from paper_1606_05732_amd import autotune
+    from paper_1606_05732_amd import workloads as W
+    log_fn("batched: generating 512 instances ...")
+    ws = W.workload5()
+    items = [(cg.CsrMatrix(torch.from_numpy(w.csr.row_ptr).cuda(),
+                           torch.from_numpy(w.csr.col_idx).cuda(),
+                           torch.from_numpy(w.csr.vals).cuda(), w.csr.n, w.csr.d),
+              w.m, w.B, w.seed) for w in ws]
+    nnz = sum(w.csr.nnz for w in ws)
+    plans = [cg.SketchPlan(X, m, B, seed) for (X, m, B, seed) in items]
+    for p in plans:
+        p.run()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    start.record()
+    for _ in range(reps):
+        for p in plans:
+            p.run()
+    stop.record()
+    stop.synchronize()
+    seq_ms = start.elapsed_time(stop) / reps
+    del plans
+    torch.cuda.empty_cache()
+    cg.set_tuning()
+    default_ms = autotune.time_batch(items, reps=5, warmup=2)
+    res = autotune.autotune_batched(items, reps=3, warmup=1)
+    tuned_ms = autotune.time_batch(items, reps=10, warmup=2)
+    log_fn(f"batched: sequential {seq_ms:.2f} ms, batch {default_ms:.2f} ms (built-in table), "
+           f"{tuned_ms:.2f} ms (autotuned in {res['seconds']:.1f} s)")
+    cls = res["classes"]
+    return {"workload": "512 CSR instances, n log-uniform [1e4, 1e6], d in {8,16,32,64}, "
+                        "density log-uniform [0.1%, 10%], m = 32, B = min(32 d^2, n/4)",
+            "instances": len(items), "nnz": nnz,
+            "sequential_ms": round(seq_ms, 3), "batched_builtin_ms": round(default_ms, 3),
+            "batched_tuned_ms": round(tuned_ms, 3),
+            "speedup_vs_sequential": round(seq_ms / tuned_ms, 2),
+            "batched_nnz_per_s": nnz / (tuned_ms * 1e-3),
+            "tuning": {f"d<=2^{c}": {"rows_per_item": res["rows_per_item"][c],
+                                     "kc": res["kc_per_item"][c]} for c in cls},
+            "autotune_trials": len(res["trials"]), "autotune_seconds": round(res["seconds"], 2)}
+
+
 def copy_calibration(mib=512, reps=3):
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters: run it under the same rocprofv3 --pmc pass as the
@@ -202,6 +254,7 @@ def main():
     ap.add_argument("--algo", default="auto", choices=["auto", "binned", "atomic", "sorted"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ladder", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -273,6 +326,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_ladder:
         result["ladder"] = ladder(max(5, args.steps // 2), 2, ev)
+    if not args.no_batched:
+        result["batched"] = batched(log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w)

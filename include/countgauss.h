@@ -191,51 +191,77 @@ int cg_sketch_adjoint_csr(const int32_t* row_ptr, const int32_t* col_idx,
                           int64_t d, int64_t m, int64_t B, uint64_t seed,
                           void* dvals, const cg_opts* opts);
 
-/* ---- many independent instances in one persistent launch --------------- */
+/* ---- many independent instances in one batch ----------------------------- *
+ * Independent CSR transforms, each with its own n, d, m, B and seed (FP32,
+ * native precision), computed together: each phase of the transform (S X
+ * count, scan, scatter and reduce; the contraction; the split reduction)
+ * is one launch over the work items of every instance, so small instances
+ * share the GPU instead of paying their own launches and tails.  Results
+ * equal those of cg_sketch_csr on each instance (S X bit for bit; the
+ * contraction up to its summation order, which depends on the tuning).   */
 typedef struct cg_instance {
   /* set by the caller */
   const int32_t* row_ptr;   /* device int32[n+1]                            */
-  const int32_t* col_idx;   /* device int32[nnz]                            */
-  const float* vals;        /* device float[nnz]                            */
+  const int32_t* col_idx;   /* device int32[nnz] (may be NULL if nnz == 0)  */
+  const float* vals;        /* device float[nnz] (may be NULL if nnz == 0)  */
   float* Y;                 /* device float[m*d], overwritten               */
-  int64_t n, d, nnz, m, B;  /* as for cg_sketch_csr (FP32, native)          */
+  int64_t n, d, nnz, m, B;  /* as for cg_sketch_csr                         */
   uint64_t seed;            /* this instance's transform                   */
-  int64_t row_offset;
+  int64_t row_offset;       /* global index of row 0                        */
   /* set by cg_batched_plan; leave them as planned */
-  int64_t sx_off;           /* byte offset of this instance's S X           */
-  int64_t part_off;         /* byte offset of its split partials            */
-  int32_t sx_tiles;         /* S X work items (row chunks)                  */
-  int32_t gsx_tiles;        /* contraction work items (column blocks of G)  */
-  int32_t kc;               /* columns of G per contraction item            */
-  int32_t first_tile;       /* index of its first S X item in the queue     */
+  int64_t ws_off;           /* byte offset of its scratch in the workspace  */
+  int64_t tile_rows;        /* rows per S X work item                       */
+  int32_t tiles;            /* S X work items (row tiles)                   */
+  int32_t ranges;           /* bucket ranges of 2^bp_shift buckets          */
+  int32_t bp_shift;
+  int32_t kc;               /* columns of G per contraction wavefront       */
+  int32_t parts;            /* contraction splits along B (4 kc columns)    */
+  int32_t gsx_items;        /* contraction work items                       */
+  int32_t red_items;        /* split-reduction work items                   */
+  int32_t first_tile;       /* its first item in each phase's queue         */
+  int32_t first_range;
+  int32_t first_gsx;
+  int32_t first_red;
+  int32_t reserved;
 } cg_instance;
 
 /*
- * Plan a batch: validate every instance, choose its tile shapes (from the
- * tuning table, see cg_set_tuning) and fill the planning fields of inst
- * (host array, in/out).  *workspace_bytes receives the workspace the
- * launch needs.  Errors: CG_EINVAL / CG_EUNSUPPORTED naming the instance.
+ * Plan a batch: validate every instance, choose its tile shapes from the
+ * tuning table (by the class ceil(log2 d) of its d) and fill the planning
+ * fields of inst (host array of count entries, in/out).  *workspace_bytes
+ * receives the workspace cg_sketch_batched needs.  Host only; queues
+ * nothing.  Errors: CG_EINVAL / CG_EUNSUPPORTED, the message naming the
+ * instance (e.g. d too large for the binned S X, a NULL pointer).
  */
 int cg_batched_plan(cg_instance* inst, int32_t count, const cg_opts* opts,
                     size_t* workspace_bytes);
 
 /*
- * One persistent launch computing every planned instance's Y (each with its
- * own seed, m, B).  inst is the host table returned by cg_batched_plan; it
- * is copied into the workspace on opts->stream and must stay valid and
- * unchanged until the stream has passed this call.  FP32 data and native
- * precision only.
+ * Compute every instance's Y.  inst is the table cg_batched_plan filled
+ * (unchanged since, with the tuning table unchanged; else CG_EINVAL); it is
+ * copied to the workspace on opts->stream, so it must stay valid until the
+ * stream has passed this call.  opts is required (workspace of at least
+ * the planned size, 256-byte aligned; precision must be native; sx_algo,
+ * kc and row_offset of opts are ignored: each instance has its own).
+ * Instances must not share a Y.  Errors as for cg_sketch_csr.
  */
 int cg_sketch_batched(const cg_instance* inst, int32_t count,
                       const cg_opts* opts);
 
 /*
- * Tuning table for the batched planner: for each d class (log2 d from 0
- * to 10) the number of rows per S X item and G columns per contraction
- * item.  NULL arguments restore the built-in table.  Host only.
+ * Tuning table of the batched planner, one entry per d class c =
+ * ceil(log2 d), c = 0 .. 10: rows_per_item[c] (rows per S X work item, a
+ * multiple of 1024 in [1024, 2^24]) and kc_per_item[c] (columns of G per
+ * contraction wavefront, a multiple of 16 in [16, 2^20]) for the first
+ * `classes` classes.  A NULL array leaves that column unchanged; both NULL
+ * restore the built-in table (16384 rows, kc 512).  Host only; plans made
+ * before a change no longer match (cg_sketch_batched rejects them).
  */
 int cg_set_tuning(const int32_t* rows_per_item, const int32_t* kc_per_item,
                   int32_t classes);
+
+/* Read the first `classes` entries of the tuning table (NULL: skipped). */
+int cg_get_tuning(int32_t* rows_per_item, int32_t* kc_per_item, int32_t classes);
 
 /* ---- test access to the random source ---------------------------------- */
 

@@ -6,6 +6,7 @@ computed by hand-written HIP kernels in libcountgauss.so (C ABI in
 include/countgauss.h).  This package is a thin binding: torch provides
 device memory and streams.
 """
-from .api import (CsrMatrix, CountGaussFn, countgauss, debug_gaussian, debug_hash,  # noqa: F401
-                  debug_philox, sketch, sketch_adjoint, sketch_adjoint_csr, SketchPlan)
+from .api import (BatchedSketch, CsrMatrix, CountGaussFn, countgauss, debug_gaussian,  # noqa: F401
+                  debug_hash, debug_philox, get_tuning, set_tuning, sketch, sketch_adjoint,
+                  sketch_adjoint_csr, sketch_batched, SketchPlan)
 from ._lib import CountGaussError, LIB_PATH  # noqa: F401

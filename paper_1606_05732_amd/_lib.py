@@ -19,6 +19,7 @@ EXPORTS = [
     "cg_opts_init", "cg_version", "cg_status_string", "cg_last_error",
     "cg_workspace_bytes", "cg_sketch_csr", "cg_sketch_dense", "cg_sketch_adjoint",
     "cg_sketch_adjoint_csr", "cg_batched_plan", "cg_sketch_batched", "cg_set_tuning",
+    "cg_get_tuning",
     "cg_debug_philox", "cg_debug_hash", "cg_debug_gaussian",
 ]
 
@@ -54,13 +55,25 @@ class CgInstance(ctypes.Structure):
         ("B", ctypes.c_int64),
         ("seed", ctypes.c_uint64),
         ("row_offset", ctypes.c_int64),
-        ("sx_off", ctypes.c_int64),
-        ("part_off", ctypes.c_int64),
-        ("sx_tiles", ctypes.c_int32),
-        ("gsx_tiles", ctypes.c_int32),
+        ("ws_off", ctypes.c_int64),
+        ("tile_rows", ctypes.c_int64),
+        ("tiles", ctypes.c_int32),
+        ("ranges", ctypes.c_int32),
+        ("bp_shift", ctypes.c_int32),
         ("kc", ctypes.c_int32),
+        ("parts", ctypes.c_int32),
+        ("gsx_items", ctypes.c_int32),
+        ("red_items", ctypes.c_int32),
         ("first_tile", ctypes.c_int32),
+        ("first_range", ctypes.c_int32),
+        ("first_gsx", ctypes.c_int32),
+        ("first_red", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
+
+
+# d classes of the batched tuning table: ceil(log2 d) = 0 .. 10
+CG_TUNING_CLASSES = 11
 
 
 class CountGaussError(RuntimeError):
@@ -112,6 +125,7 @@ def load():
         "cg_sketch_batched": (ctypes.c_int, [ctypes.POINTER(CgInstance), _I32,
                                              ctypes.POINTER(CgOpts)]),
         "cg_set_tuning": (ctypes.c_int, [ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I32]),
+        "cg_get_tuning": (ctypes.c_int, [ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I32]),
         "cg_debug_philox": (ctypes.c_int, [_U64, _P, _I64, _P, _P]),
         "cg_debug_hash": (ctypes.c_int, [_U64, _I64, _U64, _I64, _P, _P, _P]),
         "cg_debug_gaussian": (ctypes.c_int, [_U64, _I64, _I64, _I64, ctypes.c_int, _P, _P]),

@@ -303,3 +303,102 @@ class SketchPlan:
                                           ctypes.byref(self.opts))
             L.check(st, "cg_sketch_dense")
         return self.Y
+
+
+# ---------------------------------------------------------------- batched
+class BatchedSketch:
+    """Many independent CSR transforms computed together (cg_sketch_batched).
+
+    items: sequence of (X, m, B, seed) or (X, m, B, seed, row_offset) with X
+    an FP32 CsrMatrix / torch.sparse_csr on the GPU.  The plan (tile shapes
+    from the current tuning table, work items, workspace) is made once;
+    run() queues the whole batch on the current stream and returns the list
+    of Y (m x d) tensors, overwritten by each run."""
+
+    def __init__(self, items):
+        lib = L.load()
+        self.count = len(items)
+        if self.count < 1:
+            raise ValueError("a batch needs at least one instance")
+        self._table = (L.CgInstance * self.count)()
+        self._inputs = []
+        self.Y = []
+        device = None
+        for i, it in enumerate(items):
+            X, m, B, seed = it[:4]
+            row_offset = it[4] if len(it) > 4 else 0
+            csr = _as_csr(X)
+            if csr is None:
+                raise TypeError(f"instance {i}: X must be a CSR matrix")
+            _require_cuda(csr.row_ptr, csr.col_idx, csr.vals)
+            if csr.vals.dtype != torch.float32:
+                raise TypeError(f"instance {i}: batched instances are FP32")
+            if csr.row_ptr.dtype != torch.int32 or csr.col_idx.dtype != torch.int32:
+                raise TypeError(f"instance {i}: CSR indices must be int32")
+            if device is None:
+                device = csr.vals.device
+            elif csr.vals.device != device:
+                raise ValueError("all instances must be on one device")
+            Y = torch.empty((m, csr.d), dtype=torch.float32, device=device)
+            c = self._table[i]
+            c.row_ptr = csr.row_ptr.data_ptr()
+            c.col_idx = csr.col_idx.data_ptr() if csr.nnz else None
+            c.vals = csr.vals.data_ptr() if csr.nnz else None
+            c.Y = Y.data_ptr()
+            c.n, c.d, c.nnz, c.m, c.B = csr.n, csr.d, csr.nnz, m, B
+            c.seed = seed & (2 ** 64 - 1)
+            c.row_offset = row_offset
+            self._inputs.append(csr)
+            self.Y.append(Y)
+        self.device = device
+        nbytes = ctypes.c_size_t(0)
+        L.check(lib.cg_batched_plan(self._table, self.count, None, ctypes.byref(nbytes)),
+                "cg_batched_plan")
+        self._buf, self._ws, self.workspace_bytes = _workspace(nbytes.value, device)
+
+    def plan_fields(self, i):
+        """The planned fields of instance i (tile rows, tiles, ranges, kc, ...)."""
+        c = self._table[i]
+        return {k: getattr(c, k) for k in ("ws_off", "tile_rows", "tiles", "ranges", "bp_shift",
+                                           "kc", "parts", "gsx_items", "red_items")}
+
+    def run(self):
+        lib = L.load()
+        opts = L.make_opts(stream=_stream(self.device), workspace=self._ws,
+                           workspace_bytes=self.workspace_bytes)
+        L.check(lib.cg_sketch_batched(self._table, self.count, ctypes.byref(opts)),
+                "cg_sketch_batched")
+        return self.Y
+
+
+def sketch_batched(items):
+    """Y_i = T_i X_i for every (X, m, B, seed[, row_offset]) in items, as one
+    batch.  Each returned Y keeps the batch's host table and workspace
+    alive, so they outlive the queued work."""
+    plan = BatchedSketch(items)
+    Ys = plan.run()
+    for Y in Ys:
+        Y._cg_batch = plan
+    return Ys
+
+
+def set_tuning(rows_per_item=None, kc_per_item=None):
+    """Set the batched planner's tuning table (one entry per d class
+    ceil(log2 d) = 0 .. 10; shorter lists set the first classes).  Both None
+    restores the built-in table."""
+    lib = L.load()
+    if rows_per_item is None and kc_per_item is None:
+        L.check(lib.cg_set_tuning(None, None, 0), "cg_set_tuning")
+        return
+    k = len(rows_per_item if rows_per_item is not None else kc_per_item)
+    arr = lambda v: (ctypes.c_int32 * k)(*v) if v is not None else None  # noqa: E731
+    L.check(lib.cg_set_tuning(arr(rows_per_item), arr(kc_per_item), k), "cg_set_tuning")
+
+
+def get_tuning():
+    """(rows_per_item, kc_per_item) lists of the current tuning table."""
+    lib = L.load()
+    k = L.CG_TUNING_CLASSES
+    rows, kc = (ctypes.c_int32 * k)(), (ctypes.c_int32 * k)()
+    L.check(lib.cg_get_tuning(rows, kc, k), "cg_get_tuning")
+    return list(rows), list(kc)

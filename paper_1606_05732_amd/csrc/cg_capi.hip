@@ -24,6 +24,14 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+namespace cg {
+void set_last_error(const char* msg) { g_last_error = msg; }
+}  // namespace cg
+
+namespace {
+
 int hip_fail(hipError_t e, const char* where) {
   return fail(CG_EHIP, "%s: %s", where, hipGetErrorString(e));
 }

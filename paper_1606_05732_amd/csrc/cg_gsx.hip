@@ -95,18 +95,19 @@ __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int 
       }
 }
 
-// Native precision (FP32 or FP64 inputs, same-type accumulation).
+// Native precision (FP32 or FP64 inputs, same-type accumulation).  One
+// workgroup: split `bx` along B, 64-row group `group` of G, column group
+// `ng` of S X.
 template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restrict__ SX, int64_t B,
-                                                              int d, int m, int kc, Key key,
-                                                              T* __restrict__ part) {
+__device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64_t B, int d, int m,
+                                                 int kc, Key key, T* __restrict__ part, int64_t bx,
+                                                 int group, int ng) {
   using V = typename Vec4<T>::type;
   __shared__ T red[3 * 16 * NB * 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = lane & 15, kq = lane >> 4;
-  const int group = blockIdx.y;
   const uint32_t q = (uint32_t)(16 * group + p);
-  const int n0 = blockIdx.z * NB * 16;
+  const int n0 = ng * NB * 16;
   V acc[4][NB];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restric
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) col[nb] = n0 + nb * 16 + p;
 
-  const int64_t kbeg = ((int64_t)blockIdx.x * kWaves + wave) * kc;
+  const int64_t kbeg = (bx * kWaves + wave) * kc;
   const int64_t kend = min(kbeg + (int64_t)kc, B);
   for (int64_t kb = kbeg; kb < kend; kb += 4) {
     const int64_t b = kb + kq;
@@ -135,8 +136,14 @@ __global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restric
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(g[t], x[nb], acc[t][nb]);
   }
-  block_reduce_store<T, NB, V>(acc, red, wave, lane, group, n0, m, d,
-                               part + (size_t)blockIdx.x * m * d);
+  block_reduce_store<T, NB, V>(acc, red, wave, lane, group, n0, m, d, part + (size_t)bx * m * d);
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restrict__ SX, int64_t B,
+                                                              int d, int m, int kc, Key key,
+                                                              T* __restrict__ part) {
+  gsx_native_block<T, NB>(SX, B, d, m, kc, key, part, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -271,12 +278,11 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
 // depend on timing.
 constexpr int kRedWaves = 16;
 template <typename T>
-__global__ __launch_bounds__(64 * kRedWaves) void splitk_reduce_kernel(const T* __restrict__ part,
-                                                                      int64_t P, int64_t md,
-                                                                      T* __restrict__ Y) {
+__device__ __forceinline__ void splitk_reduce_block(const T* __restrict__ part, int64_t P,
+                                                    int64_t md, T* __restrict__ Y, int64_t blk) {
   __shared__ T s[kRedWaves][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t o = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t o = blk * 64 + lane;
   const int64_t p0 = P * wave / kRedWaves, p1 = P * (wave + 1) / kRedWaves;
   T acc = T(0);
   if (o < md) {
@@ -298,6 +304,37 @@ __global__ __launch_bounds__(64 * kRedWaves) void splitk_reduce_kernel(const T* 
     for (int w = 1; w < kRedWaves; ++w) y += s[w][lane];
     Y[o] = y;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * kRedWaves) void splitk_reduce_kernel(const T* __restrict__ part,
+                                                                      int64_t P, int64_t md,
+                                                                      T* __restrict__ Y) {
+  splitk_reduce_block<T>(part, P, md, Y, blockIdx.x);
+}
+
+// Batched forms: item -> instance from the item table; the local index is
+// split into (part, row group, column group) with the part fastest.
+__global__ __launch_bounds__(kThreads) void gsx_batched_kernel(const GsxArgs* __restrict__ args,
+                                                               const int32_t* __restrict__ inst,
+                                                               const int32_t* __restrict__ first) {
+  const int i = inst[blockIdx.x];
+  const GsxArgs a = args[i];
+  int64_t j = (int64_t)blockIdx.x - first[i];
+  const int64_t bx = j % a.parts;
+  j /= a.parts;
+  const int group = (int)(j % a.mgroups);
+  const int ng = (int)(j / a.mgroups);
+  gsx_native_block<float, 4>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng);
+}
+
+__global__ __launch_bounds__(64 * kRedWaves) void splitk_batched_kernel(
+    const GsxArgs* __restrict__ args, const int32_t* __restrict__ inst,
+    const int32_t* __restrict__ first) {
+  const int i = inst[blockIdx.x];
+  const GsxArgs a = args[i];
+  splitk_reduce_block<float>(a.part, a.parts, (int64_t)a.m * a.d, a.Y,
+                             (int64_t)blockIdx.x - first[i]);
 }
 
 template <typename T, int NB>
@@ -378,6 +415,19 @@ hipError_t launch_gsx_partials(const GsxPlan& pl, Prec prec, const T* SX, int64_
 template <typename T>
 hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, hipStream_t s) {
   splitk_reduce_kernel<T><<<(unsigned)((md + 63) / 64), 64 * kRedWaves, 0, s>>>(part, parts, md, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_gsx_batched(const GsxArgs* args, const int32_t* gsx_inst,
+                              const int32_t* gsx_first, int64_t items, hipStream_t s) {
+  if (items > 0) gsx_batched_kernel<<<(unsigned)items, kThreads, 0, s>>>(args, gsx_inst, gsx_first);
+  return hipGetLastError();
+}
+
+hipError_t launch_splitk_batched(const GsxArgs* args, const int32_t* red_inst,
+                                 const int32_t* red_first, int64_t items, hipStream_t s) {
+  if (items > 0)
+    splitk_batched_kernel<<<(unsigned)items, 64 * kRedWaves, 0, s>>>(args, red_inst, red_first);
   return hipGetLastError();
 }
 

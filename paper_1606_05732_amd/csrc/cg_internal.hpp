@@ -13,10 +13,13 @@ struct Key {
 };
 inline Key key_of(uint64_t seed) { return Key{(uint32_t)seed, (uint32_t)(seed >> 32)}; }
 
+// Message for cg_last_error() of the calling thread.
+void set_last_error(const char* msg);
+
 constexpr int kRowsPerWave = 256;   // rows hashed and handled per wavefront
 constexpr int kMaxD = 1024;         // widest X supported by this build
 
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ---- S X --------------------------------------------------------------
 template <typename T>
@@ -58,14 +61,56 @@ hipError_t launch_exclusive_scan(uint32_t* a, int64_t len, uint32_t* sums, hipSt
 constexpr int kBinMaxRangesCsr = 2048;
 constexpr int kBinMaxRangesDense = 2048;
 struct BinGeom {
-  int bp_shift = 0;
-  int R = 0;
-  int64_t ntiles = 0;
-  size_t lds_bytes = 0;
-  bool ok = false;
+  int bp_shift = 0;        // buckets per range = 2^bp_shift
+  int R = 0;               // ranges
+  int64_t ntiles = 0;      // row tiles
+  int64_t tile_rows = 0;   // rows per tile
+  size_t lds_bytes = 0;    // LDS of the reduce kernel
+  bool ok = false;         // this path applies
 };
-BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B);
+constexpr int64_t kBinTileRows = 16384;   // default rows per tile (a multiple of 1024)
+// tile_rows = 0 picks kBinTileRows; otherwise a multiple of 1024.
+BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B, int64_t tile_rows = 0);
 size_t binned_scratch_bytes(const BinGeom& g, int64_t count);
+
+// Everything one binned S X needs (one instance).  The scratch arrays are
+// laid out by bin_carve.
+struct BinArgs {
+  const int32_t* row_ptr;   // CSR X
+  const int32_t* col_idx;
+  const float* vals;
+  const float* X;           // dense X
+  int64_t ldx;
+  int64_t n;
+  int32_t nnz;
+  int32_t d;
+  uint32_t B;
+  Key key;
+  uint64_t row_offset;
+  int32_t bp_shift;
+  int32_t R;
+  int64_t ntiles;
+  int64_t tile_rows;
+  uint32_t* hist;   // R x ntiles: counts, then offsets inside each range
+  uint32_t* tot;    // R: items per range
+  uint32_t* hmax;   // R x ntiles: largest |value| bits (CSR)
+  uint2* items;     // one per stored entry (CSR) or row (dense)
+  float* SX;        // B x d
+};
+
+// Binned scratch at base: hist | tot | hmax | items (each 256-byte aligned).
+__host__ __device__ inline size_t bin_carve(char* base, int R, int64_t ntiles, int64_t count,
+                                            BinArgs* a) {
+  const size_t hl = align256((size_t)R * (size_t)ntiles * 4);
+  if (a) {
+    a->hist = (uint32_t*)base;
+    a->tot = (uint32_t*)(base + hl);
+    a->hmax = (uint32_t*)(base + hl + align256((size_t)R * 4));
+    a->items = (uint2*)(base + 2 * hl + align256((size_t)R * 4));
+  }
+  return 2 * hl + align256((size_t)R * 4) + align256((size_t)count * 8);
+}
+
 // `events`, if non-NULL, is the caller's stage-event array; events[1] is
 // recorded after the split plan (counts and scan).
 hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
@@ -75,6 +120,16 @@ hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, 
 hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d, uint32_t B,
                                   Key key, uint64_t row_offset, float* SX, void* scratch,
                                   hipStream_t s, void* const* events);
+
+// Binned CSR S X of many instances at once: one launch per phase over every
+// instance's work items.  args[i] is instance i (device array); tile_inst /
+// range_inst give the instance of each tile / range work item and
+// tile_first / range_first[i] the first item of instance i.  r_max and
+// reduce_lds are the largest R and reduce LDS over the batch.
+hipError_t launch_sx_binned_batched(const BinArgs* args, const int32_t* tile_inst,
+                                    const int32_t* tile_first, int64_t tiles,
+                                    const int32_t* range_inst, const int32_t* range_first,
+                                    int64_t ranges, int r_max, size_t reduce_lds, hipStream_t s);
 
 // ---- G (S X) -----------------------------------------------------------
 enum class Prec { Native, BF16, FP8 };
@@ -97,6 +152,23 @@ hipError_t launch_gsx_partials(const GsxPlan& plan, Prec prec, const T* SX, int6
 // ... and Y = sum over p of part[p] in increasing p.
 template <typename T>
 hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, hipStream_t s);
+
+// Contraction of many instances (FP32, native precision).  Instance i:
+// Y_i = G_i SX_i with its own key, split over B into `parts` chunks of
+// 4 kc columns; its work items are parts x mgroups x ngroups (64 rows of G
+// by 64 columns of S X each), then ceil(m d / 64) reduction items.
+struct GsxArgs {
+  const float* SX;
+  float* part;   // parts x m x d
+  float* Y;      // m x d
+  int64_t B;
+  int32_t d, m, kc, parts, mgroups, ngroups;
+  Key key;
+};
+hipError_t launch_gsx_batched(const GsxArgs* args, const int32_t* gsx_inst,
+                              const int32_t* gsx_first, int64_t items, hipStream_t s);
+hipError_t launch_splitk_batched(const GsxArgs* args, const int32_t* red_inst,
+                                 const int32_t* red_first, int64_t items, hipStream_t s);
 
 // ---- adjoint ----------------------------------------------------------
 template <typename T>

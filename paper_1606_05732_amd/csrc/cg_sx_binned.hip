@@ -45,6 +45,8 @@
 // columns >= d) never causes an out-of-bounds access: row starts are
 // clamped, windows are bounded, columns out of range contribute nothing.
 // The result is then unspecified.
+#include <algorithm>
+
 #include "cg_internal.hpp"
 #include "cg_rng.hpp"
 
@@ -161,16 +163,21 @@ __device__ __forceinline__ void lane_hashes(int64_t r, int64_t t1, uint64_t row_
 // hist[p * ntiles + t] = items of tile t that fall in range p.  Two rounds
 // per iteration, so each wavefront has ten row_ptr loads in flight.
 template <bool CSR>
-__global__ __launch_bounds__(kSThreads) void bin_count_kernel(
-    const int32_t* __restrict__ row_ptr, int64_t n, int32_t nnz, uint32_t B, Key key,
-    uint64_t row_offset, int bp_shift, int R, int64_t ntiles, uint32_t* __restrict__ hist) {
+__device__ __forceinline__ void count_tile(const BinArgs& a, int64_t tile) {
+  const int32_t* __restrict__ row_ptr = a.row_ptr;
+  const int64_t n = a.n;
+  const int32_t nnz = a.nnz;
+  const uint32_t B = a.B;
+  const Key key = a.key;
+  const uint64_t row_offset = a.row_offset;
+  const int bp_shift = a.bp_shift, R = a.R;
   uint32_t* s_cnt = (uint32_t*)dyn_lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int32_t* w = (int32_t*)(s_cnt + R) + wave * 2 * kRpWin;
   for (int i = threadIdx.x; i < R; i += kSThreads) s_cnt[i] = 0;
   __syncthreads();
-  const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
-  const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
+  const int64_t t0 = tile * a.tile_rows;
+  const int64_t t1 = min(t0 + a.tile_rows, n);
   for (int64_t round = t0; round < t1; round += 2 * kRoundRows) {
     const int64_t ra = round + (int64_t)kWaveRows * wave, rb = ra + kRoundRows;
     RpLoad la, lb;
@@ -195,17 +202,21 @@ __global__ __launch_bounds__(kSThreads) void bin_count_kernel(
     }
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < R; p += kSThreads) hist[(int64_t)p * ntiles + blockIdx.x] = s_cnt[p];
+  for (int p = threadIdx.x; p < R; p += kSThreads) a.hist[(int64_t)p * a.ntiles + tile] = s_cnt[p];
+}
+
+template <bool CSR>
+__global__ __launch_bounds__(kSThreads) void bin_count_kernel(BinArgs a) {
+  count_tile<CSR>(a, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ scan
 // Workgroup p: hist[p][0 .. ntiles) becomes its exclusive prefix sums and
 // tot[p] the range's item count.
-__global__ __launch_bounds__(kSThreads) void bin_scan_kernel(uint32_t* __restrict__ hist,
-                                                             int64_t ntiles,
-                                                             uint32_t* __restrict__ tot) {
+__device__ __forceinline__ void scan_range(const BinArgs& a, int p) {
   __shared__ uint32_t s_w[kSWaves];
-  uint32_t* h = hist + (int64_t)blockIdx.x * ntiles;
+  const int64_t ntiles = a.ntiles;
+  uint32_t* h = a.hist + (int64_t)p * ntiles;
   uint32_t carry = 0;
   for (int64_t c0 = 0; c0 < ntiles; c0 += 4 * kSThreads) {
     const int64_t i = c0 + 4 * (int64_t)threadIdx.x;
@@ -224,8 +235,10 @@ __global__ __launch_bounds__(kSThreads) void bin_scan_kernel(uint32_t* __restric
     }
     carry += all;
   }
-  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+  if (threadIdx.x == 0) a.tot[p] = carry;
 }
+
+__global__ __launch_bounds__(kSThreads) void bin_scan_kernel(BinArgs a) { scan_range(a, blockIdx.x); }
 
 // ------------------------------------------------------------------ scatter
 // LDS of the scatter kernels:
@@ -291,7 +304,7 @@ __device__ __forceinline__ ScatterLds carve_scatter(int R, bool csr) {
 // made the counts exceed nnz).  Also clears the per-range round state.
 __device__ __forceinline__ void load_windows(const ScatterLds& L, const uint32_t* __restrict__ offs,
                                              const uint32_t* __restrict__ tot, int R,
-                                             int64_t ntiles, uint32_t total) {
+                                             int64_t ntiles, uint32_t total, int64_t t) {
   const int per = (R + kSThreads - 1) / kSThreads;
   const int b = (int)threadIdx.x * per;
   uint32_t local = 0;
@@ -299,7 +312,6 @@ __device__ __forceinline__ void load_windows(const ScatterLds& L, const uint32_t
     if (b + k < R) local += tot[b + k];
   uint32_t all;
   uint64_t base = block_exscan<kSThreads>(local, L.s_w, &all);
-  const int64_t t = blockIdx.x;
   for (int k = 0; k < per; ++k) {
     const int p = b + k;
     if (p >= R) break;
@@ -366,20 +378,26 @@ __device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t
 // round's entries -- one contiguous segment of col_idx/vals -- are copied
 // into LDS in chunks of kInCap with coalesced loads, and every lane then
 // walks its own rows' entries there and stages the items.
-__global__ __launch_bounds__(kSThreads) void bin_scatter_csr_kernel(
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-    const float* __restrict__ vals, int64_t n, int32_t nnz, int d, uint32_t B, Key key,
-    uint64_t row_offset, int bp_shift, int R, int64_t ntiles, const uint32_t* __restrict__ offs,
-    const uint32_t* __restrict__ tot, uint32_t total, uint2* __restrict__ items,
-    uint32_t* __restrict__ hmax) {
+__device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile) {
+  const int32_t* __restrict__ row_ptr = a.row_ptr;
+  const int32_t* __restrict__ col_idx = a.col_idx;
+  const float* __restrict__ vals = a.vals;
+  const int64_t n = a.n;
+  const int32_t nnz = a.nnz;
+  const int d = a.d;
+  const uint32_t B = a.B;
+  const Key key = a.key;
+  const uint64_t row_offset = a.row_offset;
+  const int bp_shift = a.bp_shift, R = a.R;
+  uint2* __restrict__ items = a.items;
   const ScatterLds L = carve_scatter(R, true);
   const uint32_t cap = (uint32_t)stage_cap(R, true);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int32_t* w = L.rpw + wave * kRpWin;
-  load_windows(L, offs, tot, R, ntiles, total);
+  load_windows(L, a.hist, a.tot, R, a.ntiles, (uint32_t)nnz, tile);
   const uint32_t bmask = (1u << bp_shift) - 1u;
-  const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
-  const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
+  const int64_t t0 = tile * a.tile_rows;
+  const int64_t t1 = min(t0 + a.tile_rows, n);
   for (int64_t round = t0; round < t1; round += kRoundRows) {
     const int64_t r0 = round + (int64_t)kWaveRows * wave;
     const RpLoad rl = load_row_ptr(row_ptr, r0, t1);
@@ -467,19 +485,26 @@ __global__ __launch_bounds__(kSThreads) void bin_scatter_csr_kernel(
     flush_stage(L, R, staged ? E : 0u, false, items);
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < R; q += kSThreads) hmax[(int64_t)q * ntiles + blockIdx.x] = L.r_max[q];
+  for (int q = threadIdx.x; q < R; q += kSThreads) a.hmax[(int64_t)q * a.ntiles + tile] = L.r_max[q];
+}
+
+__global__ __launch_bounds__(kSThreads) void bin_scatter_csr_kernel(BinArgs a) {
+  scatter_csr_tile(a, blockIdx.x);
 }
 
 // Dense.  A round is 1024 rows, four per lane, one item per row.
-__global__ __launch_bounds__(kSThreads) void bin_scatter_dense_kernel(
-    int64_t n, uint32_t B, Key key, uint64_t row_offset, int bp_shift, int R, int64_t ntiles,
-    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ tot, uint32_t total,
-    uint2* __restrict__ items) {
+__device__ __forceinline__ void scatter_dense_tile(const BinArgs& a, int64_t tile) {
+  const int64_t n = a.n;
+  const uint32_t B = a.B;
+  const Key key = a.key;
+  const uint64_t row_offset = a.row_offset;
+  const int bp_shift = a.bp_shift, R = a.R;
+  uint2* __restrict__ items = a.items;
   const ScatterLds L = carve_scatter(R, false);
-  load_windows(L, offs, tot, R, ntiles, total);
+  load_windows(L, a.hist, a.tot, R, a.ntiles, (uint32_t)n, tile);
   const uint32_t bmask = (1u << bp_shift) - 1u;
-  const int64_t t0 = (int64_t)blockIdx.x * kTileRows;
-  const int64_t t1 = min(t0 + (int64_t)kTileRows, n);
+  const int64_t t0 = tile * a.tile_rows;
+  const int64_t t1 = min(t0 + a.tile_rows, n);
   for (int64_t round = t0; round < t1; round += kRoundRows) {
     const int64_t r = round + (int64_t)kRPT * threadIdx.x;
     uint32_t hv[kRPT];
@@ -504,6 +529,10 @@ __global__ __launch_bounds__(kSThreads) void bin_scatter_dense_kernel(
     __syncthreads();
     flush_stage(L, R, E, true, items);
   }
+}
+
+__global__ __launch_bounds__(kSThreads) void bin_scatter_dense_kernel(BinArgs a) {
+  scatter_dense_tile(a, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ reduce
@@ -542,14 +571,17 @@ __device__ __forceinline__ void range_of(const uint32_t* __restrict__ tot, int p
   *end = (uint32_t)min(max(e, (uint64_t)*start), (uint64_t)total);
 }
 
-__global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(
-    const uint2* __restrict__ items, const uint32_t* __restrict__ tot,
-    const uint32_t* __restrict__ hmax, int64_t ntiles, uint32_t total, uint32_t B, int d,
-    int bp_shift, float* __restrict__ SX) {
+__device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p) {
+  const uint2* __restrict__ items = a.items;
+  const uint32_t* __restrict__ tot = a.tot;
+  const uint32_t* __restrict__ hmax = a.hmax;
+  const int64_t ntiles = a.ntiles;
+  const uint32_t total = (uint32_t)a.nnz, B = a.B;
+  const int d = a.d, bp_shift = a.bp_shift;
+  float* __restrict__ SX = a.SX;
   unsigned long long* s_acc = (unsigned long long*)dyn_lds;
   __shared__ uint32_t s_red[kWaves];
   __shared__ uint64_t s_red64[kWaves];
-  const int p = blockIdx.x;
   const int cells = (1 << bp_shift) * d;
   for (int i = threadIdx.x; i < cells; i += kThreads) s_acc[i] = 0ull;
   uint32_t mx = 0;
@@ -605,6 +637,10 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(
   }
 }
 
+__global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(BinArgs a) {
+  reduce_csr_range(a, blockIdx.x);
+}
+
 // Dense LDS: slice Bp*d floats | rows and their buckets (kDenseCap) |
 // cnt, off, fill (Bp each) | block scan
 __host__ __device__ inline size_t dense_reduce_lds_bytes(int Bp, int d) {
@@ -612,10 +648,14 @@ __host__ __device__ inline size_t dense_reduce_lds_bytes(int Bp, int d) {
 }
 
 template <int LPR>
-__global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(
-    const float* __restrict__ X, int64_t ldx, int64_t n, const uint2* __restrict__ items,
-    const uint32_t* __restrict__ tot, uint32_t total, uint32_t B, int d, int bp_shift,
-    float* __restrict__ SX) {
+__device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
+  const float* __restrict__ X = a.X;
+  const int64_t ldx = a.ldx, n = a.n;
+  const uint2* __restrict__ items = a.items;
+  const uint32_t* __restrict__ tot = a.tot;
+  const uint32_t total = (uint32_t)n, B = a.B;
+  const int d = a.d, bp_shift = a.bp_shift;
+  float* __restrict__ SX = a.SX;
   constexpr int RPP = 64 / LPR;                // rows per instruction (one per lane group)
   constexpr int U = RPP >= 8 ? 4 : 16 / RPP;   // row loads in flight per lane group
   constexpr int PER = kDenseCap / kThreads;    // items held per thread
@@ -629,7 +669,6 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(
   uint32_t* off = cnt + Bp;
   uint32_t* fill = off + Bp;
   uint32_t* s_w = fill + Bp;
-  const int p = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = lane / LPR, c = lane % LPR;
   const bool cok = c < d;
@@ -714,30 +753,15 @@ __global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(
   }
 }
 
+template <int LPR>
+__global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(BinArgs a) {
+  reduce_dense_range<LPR>(a, blockIdx.x);
+}
+
 int lanes_per_row(int d) {
   int l = 1;
   while (l < d && l < 64) l <<= 1;
   return l;
-}
-
-// Scratch: hist (R x ntiles) | tot (R) | hmax (R x ntiles) | items
-struct Carve {
-  uint32_t *hist, *tot, *hmax;
-  uint2* items;
-};
-
-Carve carve(void* base, const BinGeom& g) {
-  char* p = (char*)base;
-  Carve c;
-  const int64_t hl = (int64_t)g.R * g.ntiles;
-  c.hist = (uint32_t*)p;
-  p += align256((size_t)hl * 4);
-  c.tot = (uint32_t*)p;
-  p += align256((size_t)g.R * 4);
-  c.hmax = (uint32_t*)p;
-  p += align256((size_t)hl * 4);
-  c.items = (uint2*)p;
-  return c;
 }
 
 // Kernels using more than 64 KB of LDS say so before their launch.
@@ -750,9 +774,44 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 
 size_t count_lds_bytes(int R) { return (size_t)R * 4 + (size_t)kSWaves * 2 * kRpWin * 4; }
 
+// ------------------------------------------------------------------ batched
+// One workgroup per work item of any instance: item -> instance from the
+// item table, local index = item - first item of that instance.
+__global__ __launch_bounds__(kSThreads) void bin_count_batched(const BinArgs* __restrict__ args,
+                                                               const int32_t* __restrict__ inst,
+                                                               const int32_t* __restrict__ first) {
+  const int i = inst[blockIdx.x];
+  const BinArgs a = args[i];
+  count_tile<true>(a, (int64_t)blockIdx.x - first[i]);
+}
+
+__global__ __launch_bounds__(kSThreads) void bin_scan_batched(const BinArgs* __restrict__ args,
+                                                              const int32_t* __restrict__ inst,
+                                                              const int32_t* __restrict__ first) {
+  const int i = inst[blockIdx.x];
+  const BinArgs a = args[i];
+  scan_range(a, (int)((int64_t)blockIdx.x - first[i]));
+}
+
+__global__ __launch_bounds__(kSThreads) void bin_scatter_batched(const BinArgs* __restrict__ args,
+                                                                 const int32_t* __restrict__ inst,
+                                                                 const int32_t* __restrict__ first) {
+  const int i = inst[blockIdx.x];
+  const BinArgs a = args[i];
+  scatter_csr_tile(a, (int64_t)blockIdx.x - first[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void bin_reduce_batched(const BinArgs* __restrict__ args,
+                                                               const int32_t* __restrict__ inst,
+                                                               const int32_t* __restrict__ first) {
+  const int i = inst[blockIdx.x];
+  const BinArgs a = args[i];
+  reduce_csr_range(a, (int)((int64_t)blockIdx.x - first[i]));
+}
+
 }  // namespace
 
-BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B) {
+BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B, int64_t tile_rows) {
   BinGeom g;
   int shift = 0;
   if (csr) {
@@ -764,16 +823,34 @@ BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B) {
   }
   g.bp_shift = shift;
   g.R = (int)((B + ((int64_t)1 << shift) - 1) >> shift);
-  g.ntiles = (n + kTileRows - 1) / kTileRows;
+  g.tile_rows = tile_rows > 0 ? tile_rows : kBinTileRows;
+  g.ntiles = (n + g.tile_rows - 1) / g.tile_rows;
   g.ok = g.R <= (csr ? kBinMaxRangesCsr : kBinMaxRangesDense) && d <= (csr ? kMaxD : 64) &&
          n < ((int64_t)1 << 31) && (int64_t)g.R * g.ntiles < ((int64_t)1 << 30) &&
+         g.tile_rows % kRoundRows == 0 && g.tile_rows <= ((int64_t)1 << 24) &&
          scatter_lds_bytes(g.R, csr) <= 160 * 1024 && stage_cap(g.R, csr) >= kRoundRows;
   return g;
 }
 
 size_t binned_scratch_bytes(const BinGeom& g, int64_t count) {
-  const int64_t hl = (int64_t)g.R * g.ntiles;
-  return 2 * align256((size_t)hl * 4) + align256((size_t)g.R * 4) + align256((size_t)count * 8);
+  return bin_carve(nullptr, g.R, g.ntiles, count, nullptr);
+}
+
+static BinArgs make_args(const BinGeom& g, int64_t n, int d, uint32_t B, Key key,
+                         uint64_t row_offset, float* SX, void* scratch, int64_t count) {
+  BinArgs a{};
+  a.n = n;
+  a.d = d;
+  a.B = B;
+  a.key = key;
+  a.row_offset = row_offset;
+  a.bp_shift = g.bp_shift;
+  a.R = g.R;
+  a.ntiles = g.ntiles;
+  a.tile_rows = g.tile_rows;
+  a.SX = SX;
+  bin_carve((char*)scratch, g.R, g.ntiles, count, &a);
+  return a;
 }
 
 hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
@@ -781,21 +858,21 @@ hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, 
                                 uint64_t row_offset, float* SX, void* scratch, hipStream_t s,
                                 void* const* events) {
   const BinGeom g = bin_geometry(true, n, d, B);
-  Carve c = carve(scratch, g);
+  BinArgs a = make_args(g, n, d, B, key, row_offset, SX, scratch, nnz);
+  a.row_ptr = row_ptr;
+  a.col_idx = col_idx;
+  a.vals = vals;
+  a.nnz = (int32_t)nnz;
   const size_t sl = scatter_lds_bytes(g.R, true), cl = count_lds_bytes(g.R);
   hipError_t e;
   if ((e = allow_lds(bin_count_kernel<true>, cl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_scatter_csr_kernel, sl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_reduce_csr_kernel, g.lds_bytes)) != hipSuccess) return e;
-  bin_count_kernel<true><<<(unsigned)g.ntiles, kSThreads, cl, s>>>(
-      row_ptr, n, (int32_t)nnz, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist);
-  bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(c.hist, g.ntiles, c.tot);
+  bin_count_kernel<true><<<(unsigned)g.ntiles, kSThreads, cl, s>>>(a);
+  bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(a);
   if (events && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
-  bin_scatter_csr_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(
-      row_ptr, col_idx, vals, n, (int32_t)nnz, d, B, key, row_offset, g.bp_shift, g.R, g.ntiles,
-      c.hist, c.tot, (uint32_t)nnz, c.items, c.hmax);
-  bin_reduce_csr_kernel<<<(unsigned)g.R, kThreads, g.lds_bytes, s>>>(
-      c.items, c.tot, c.hmax, g.ntiles, (uint32_t)nnz, B, d, g.bp_shift, SX);
+  bin_scatter_csr_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(a);
+  bin_reduce_csr_kernel<<<(unsigned)g.R, kThreads, g.lds_bytes, s>>>(a);
   return hipGetLastError();
 }
 
@@ -803,23 +880,22 @@ hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d,
                                   Key key, uint64_t row_offset, float* SX, void* scratch,
                                   hipStream_t s, void* const* events) {
   const BinGeom g = bin_geometry(false, n, d, B);
-  Carve c = carve(scratch, g);
+  BinArgs a = make_args(g, n, d, B, key, row_offset, SX, scratch, n);
+  a.X = X;
+  a.ldx = ldx;
   const size_t sl = scatter_lds_bytes(g.R, false), cl = count_lds_bytes(g.R);
   hipError_t e;
   if ((e = allow_lds(bin_count_kernel<false>, cl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_scatter_dense_kernel, sl)) != hipSuccess) return e;
-  bin_count_kernel<false><<<(unsigned)g.ntiles, kSThreads, cl, s>>>(
-      nullptr, n, 0, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist);
-  bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(c.hist, g.ntiles, c.tot);
+  bin_count_kernel<false><<<(unsigned)g.ntiles, kSThreads, cl, s>>>(a);
+  bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(a);
   if (events && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
-  bin_scatter_dense_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(
-      n, B, key, row_offset, g.bp_shift, g.R, g.ntiles, c.hist, c.tot, (uint32_t)n, c.items);
+  bin_scatter_dense_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(a);
   const unsigned gr = (unsigned)g.R;
   const size_t rl = g.lds_bytes;
-#define CG_DENSE_REDUCE(L)                                                                     \
-  if ((e = allow_lds(bin_reduce_dense_kernel<L>, rl)) != hipSuccess) return e;                 \
-  bin_reduce_dense_kernel<L><<<gr, kThreads, rl, s>>>(X, ldx, n, c.items, c.tot, (uint32_t)n, \
-                                                      B, d, g.bp_shift, SX);
+#define CG_DENSE_REDUCE(L)                                                     \
+  if ((e = allow_lds(bin_reduce_dense_kernel<L>, rl)) != hipSuccess) return e; \
+  bin_reduce_dense_kernel<L><<<gr, kThreads, rl, s>>>(a);
   switch (lanes_per_row(d)) {
     case 1: CG_DENSE_REDUCE(1) break;
     case 2: CG_DENSE_REDUCE(2) break;
@@ -830,6 +906,27 @@ hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d,
     default: CG_DENSE_REDUCE(64) break;
   }
 #undef CG_DENSE_REDUCE
+  return hipGetLastError();
+}
+
+hipError_t launch_sx_binned_batched(const BinArgs* args, const int32_t* tile_inst,
+                                    const int32_t* tile_first, int64_t tiles,
+                                    const int32_t* range_inst, const int32_t* range_first,
+                                    int64_t ranges, int r_max, size_t reduce_lds, hipStream_t s) {
+  // every instance's scatter layout fits: scatter_lds_bytes(R) <= max(kScatterLds,
+  // scatter_lds_bytes(r_max)) for R <= r_max (the stage only shrinks to its floor
+  // as R grows); count_lds_bytes grows with R
+  const size_t sl = std::max(scatter_lds_bytes(r_max, true), kScatterLds);
+  const size_t cl = count_lds_bytes(r_max);
+  hipError_t e;
+  if ((e = allow_lds(bin_count_batched, cl)) != hipSuccess) return e;
+  if ((e = allow_lds(bin_scatter_batched, sl)) != hipSuccess) return e;
+  if ((e = allow_lds(bin_reduce_batched, reduce_lds)) != hipSuccess) return e;
+  if (tiles > 0) bin_count_batched<<<(unsigned)tiles, kSThreads, cl, s>>>(args, tile_inst, tile_first);
+  if (ranges > 0) bin_scan_batched<<<(unsigned)ranges, kSThreads, 0, s>>>(args, range_inst, range_first);
+  if (tiles > 0) bin_scatter_batched<<<(unsigned)tiles, kSThreads, sl, s>>>(args, tile_inst, tile_first);
+  if (ranges > 0)
+    bin_reduce_batched<<<(unsigned)ranges, kThreads, reduce_lds, s>>>(args, range_inst, range_first);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ def test_version_and_status_strings():
 def test_opts_struct_matches_header_size():
     # uint32 + 3 int32, then six 8-byte fields
     assert ctypes.sizeof(L.CgOpts) == 64
-    assert ctypes.sizeof(L.CgInstance) == 120
+    assert ctypes.sizeof(L.CgInstance) == 152
 
 
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
