@@ -69,7 +69,7 @@ constexpr int kMinStage = 1024;                // smallest output stage (items)
 constexpr int kDenseCap = 8192;                // items sorted per dense reduce pass
 
 static_assert(kTileRows % kRoundRows == 0, "tiles hold whole rounds");
-static_assert(kInCap % kSThreads == 0, "input chunk is whole per-thread steps");
+static_assert(kInCap % (4 * kSThreads) == 0, "input chunk is whole 16-byte steps per thread");
 static_assert(kRPT == 2 || kRPT % 4 == 0, "rows per thread: 2 or whole Philox blocks");
 
 extern __shared__ __align__(16) unsigned char dyn_lds[];
@@ -112,39 +112,67 @@ __device__ uint32_t block_exscan(uint32_t v, uint32_t* s_w, uint32_t* total) {
 }
 
 // ------------------------------------------------------------------ row_ptr
-// row_ptr of the wavefront's kWaveRows rows from r0 (kWaveRows + 1 values,
-// indices clamped to t1 so rows at or past t1 come out empty), read
-// lane-contiguous.
+// Row starts of the wavefront's kWaveRows rows from r0; lane l gets those of
+// its rows r0 + kRPT l + j (j = 0 .. kRPT) -- rows at or past t1 come out
+// empty (their starts are clamped to row_ptr[t1]).
+//  vec: row_ptr is 16-byte aligned and kRPT == 4: one 16-byte load per lane
+//       (the lane's own four starts) and the fifth from the next lane.
+//  otherwise: lane-contiguous 4-byte loads handed over through the
+//       wavefront's LDS window (kRpWin words).
 struct RpLoad {
   int32_t v[kRPT];
   int32_t last;
+  bool direct;   // v holds the lane's own row starts (16-byte load)
 };
 
+// The choice is uniform over the wavefront (all its rows before t1), so the
+// 16-byte load is not guarded per lane: a guarded load would be waited for
+// at the end of its branch.
 __device__ __forceinline__ RpLoad load_row_ptr(const int32_t* __restrict__ row_ptr, int64_t r0,
-                                               int64_t t1) {
+                                               int64_t t1, bool vec) {
   const int lane = threadIdx.x & 63;
   RpLoad l;
+  // (readfirstlane tells the compiler the choice is uniform, so it keeps two
+  // paths instead of merging their loads into 4-byte ones)
+  l.direct = __builtin_amdgcn_readfirstlane((int)(kRPT == 4 && vec && r0 + kWaveRows <= t1)) != 0;
+  if (l.direct) {
+    typedef int32_t v4i __attribute__((ext_vector_type(4)));
+    const v4i q = __builtin_nontemporal_load((const v4i*)(row_ptr + r0 + kRPT * lane));
+    l.v[0] = q[0];
+    l.v[1] = q[1];
+    l.v[2] = q[2];
+    l.v[3] = q[3];
+  } else {
 #pragma unroll
-  for (int j = 0; j < kRPT; ++j) l.v[j] = row_ptr[min(r0 + lane + 64 * j, t1)];
+    for (int j = 0; j < kRPT; ++j) l.v[j] = row_ptr[min(r0 + lane + 64 * j, t1)];
+  }
   l.last = row_ptr[min(r0 + kWaveRows, t1)];
   return l;
 }
 
-// Hands lane l the row starts rp[0 .. kRPT] of rows r0 + kRPT l + j through
-// the wavefront's LDS window w (kRpWin words).  Values are clamped to
-// [0, nnz] and made non-decreasing, so row lengths are never negative.
+// Values are clamped to [0, nnz] and made non-decreasing, so row lengths
+// are never negative.
 __device__ __forceinline__ void transpose_row_ptr(const RpLoad& l, int32_t* w, int32_t nnz,
                                                   int32_t rp[kRPT + 1]) {
   const int lane = threadIdx.x & 63;
+  if (l.direct) {
+    const int32_t nxt = __shfl_down(l.v[0], 1, 64);
 #pragma unroll
-  for (int j = 0; j < kRPT; ++j) w[lane + 64 * j] = l.v[j];
-  if (lane == 0) w[kWaveRows] = l.last;
-  wave_sync();
+    for (int j = 0; j < kRPT; ++j) rp[j] = l.v[j];
+    rp[kRPT] = lane == 63 ? l.last : nxt;
+  } else {
 #pragma unroll
-  for (int j = 0; j <= kRPT; ++j) rp[j] = min(max(w[kRPT * lane + j], 0), nnz);
+    for (int j = 0; j < kRPT; ++j) w[lane + 64 * j] = l.v[j];
+    if (lane == 0) w[kWaveRows] = l.last;
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j <= kRPT; ++j) rp[j] = w[kRPT * lane + j];
+    wave_sync();
+  }
+#pragma unroll
+  for (int j = 0; j <= kRPT; ++j) rp[j] = min(max(rp[j], 0), nnz);
 #pragma unroll
   for (int j = 1; j <= kRPT; ++j) rp[j] = max(rp[j], rp[j - 1]);
-  wave_sync();
 }
 
 // Packed hashes of this lane's kRPT rows r .. r + kRPT - 1 (zero past t1).
@@ -178,12 +206,13 @@ __device__ __forceinline__ void count_tile(const BinArgs& a, int64_t tile) {
   __syncthreads();
   const int64_t t0 = tile * a.tile_rows;
   const int64_t t1 = min(t0 + a.tile_rows, n);
+  const bool vec = ((uintptr_t)row_ptr & 15) == 0;
   for (int64_t round = t0; round < t1; round += 2 * kRoundRows) {
     const int64_t ra = round + (int64_t)kWaveRows * wave, rb = ra + kRoundRows;
     RpLoad la, lb;
     if (CSR) {
-      la = load_row_ptr(row_ptr, ra, t1);
-      lb = load_row_ptr(row_ptr, rb, t1);
+      la = load_row_ptr(row_ptr, ra, t1, vec);
+      lb = load_row_ptr(row_ptr, rb, t1, vec);
     }
     uint32_t ha[kRPT], hb[kRPT];
     lane_hashes(ra + kRPT * lane, t1, row_offset, B, key, ha);
@@ -398,9 +427,12 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
   const uint32_t bmask = (1u << bp_shift) - 1u;
   const int64_t t0 = tile * a.tile_rows;
   const int64_t t1 = min(t0 + a.tile_rows, n);
+  const bool vec = ((uintptr_t)row_ptr & 15) == 0;
+  // 16-byte loads of the entries: chunks then start at multiples of 4
+  const bool vecx = (((uintptr_t)col_idx | (uintptr_t)vals) & 15) == 0;
   for (int64_t round = t0; round < t1; round += kRoundRows) {
     const int64_t r0 = round + (int64_t)kWaveRows * wave;
-    const RpLoad rl = load_row_ptr(row_ptr, r0, t1);
+    const RpLoad rl = load_row_ptr(row_ptr, r0, t1, vec);
     uint32_t hv[kRPT];
     lane_hashes(r0 + kRPT * lane, t1, row_offset, B, key, hv);
     __syncthreads();   // the previous round's flush is done with the LDS state
@@ -429,21 +461,47 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
     }
     const int32_t S0 = L.s_seg[0];
     const int32_t S1 = max(L.s_seg[1], S0);
-    for (int32_t c0 = S0; c0 < S1; c0 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1)) {
+    const int32_t A = vecx ? (S0 & ~3) : S0;
+    for (int32_t c0 = A; c0 < S1; c0 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1)) {
       const int32_t c1 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1);
-      if (c0 != S0) __syncthreads();   // every lane is done with the previous chunk
-      int32_t cc[kInCap / kSThreads];
-      float vv[kInCap / kSThreads];
+      if (c0 != A) __syncthreads();   // every lane is done with the previous chunk
+      if (vecx && c0 + kInCap <= nnz) {
+        // a whole chunk inside the arrays (uniform over the workgroup):
+        // thread t stages entries c0 + 4 t + 4 kSThreads u + (0 .. 3) with one
+        // unguarded 16-byte load of each array; entries outside [S0, S1) are
+        // staged but never read
+        constexpr int G = kInCap / (4 * kSThreads);
+        int4 cq[G];
+        float4 vq[G];
 #pragma unroll
-      for (int u = 0; u < kInCap / kSThreads; ++u) {
-        const int32_t k = min(c0 + (int32_t)threadIdx.x + u * kSThreads, c1 - 1);
-        cc[u] = col_idx[k];
-        vv[u] = vals[k];
-      }
+        for (int u = 0; u < G; ++u) {
+          const int32_t g = c0 + 4 * ((int32_t)threadIdx.x + u * kSThreads);
+          cq[u] = *(const int4*)(col_idx + g);
+          vq[u] = *(const float4*)(vals + g);
+        }
+        uint4* in4 = (uint4*)L.in;
 #pragma unroll
-      for (int u = 0; u < kInCap / kSThreads; ++u) {
-        const int32_t i = (int32_t)threadIdx.x + u * kSThreads;
-        if (i < c1 - c0) L.in[i] = make_uint2((uint32_t)cc[u], __float_as_uint(vv[u]));
+        for (int u = 0; u < G; ++u) {
+          const int32_t i2 = 2 * ((int32_t)threadIdx.x + u * kSThreads);
+          in4[i2] = make_uint4((uint32_t)cq[u].x, __float_as_uint(vq[u].x), (uint32_t)cq[u].y,
+                               __float_as_uint(vq[u].y));
+          in4[i2 + 1] = make_uint4((uint32_t)cq[u].z, __float_as_uint(vq[u].z), (uint32_t)cq[u].w,
+                                   __float_as_uint(vq[u].w));
+        }
+      } else {
+        int32_t cc[kInCap / kSThreads];
+        float vv[kInCap / kSThreads];
+#pragma unroll
+        for (int u = 0; u < kInCap / kSThreads; ++u) {
+          const int32_t k = min(c0 + (int32_t)threadIdx.x + u * kSThreads, c1 - 1);
+          cc[u] = col_idx[k];
+          vv[u] = vals[k];
+        }
+#pragma unroll
+        for (int u = 0; u < kInCap / kSThreads; ++u) {
+          const int32_t i = (int32_t)threadIdx.x + u * kSThreads;
+          if (i < c1 - c0) L.in[i] = make_uint2((uint32_t)cc[u], __float_as_uint(vv[u]));
+        }
       }
       __syncthreads();
       const int32_t a = max(rp[0], c0), e = min(rp[kRPT], c1);
@@ -613,22 +671,33 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p) {
   while (lg < 32 && (1u << lg) < count) ++lg;
   const int f = 61 - E - lg;
   const double scale = ldexp(1.0, f), inv = ldexp(1.0, -f);
-  constexpr int UR = 8;
-  uint32_t i = start + threadIdx.x;
-  for (; i + (UR - 1) * kThreads < end; i += UR * kThreads) {
-    uint2 it[UR];
-#pragma unroll
-    for (int u = 0; u < UR; ++u) it[u] = items[i + u * kThreads];
-#pragma unroll
-    for (int u = 0; u < UR; ++u)
-      if (it[u].x < (uint32_t)cells)
-        atomicAdd(&s_acc[it[u].x],
-                  (unsigned long long)__double2ll_rn((double)__uint_as_float(it[u].y) * scale));
-  }
-  for (; i < end; i += kThreads) {
-    const uint2 it = items[i];
+  auto add = [&](uint2 it) {
     if (it.x < (uint32_t)cells)
       atomicAdd(&s_acc[it.x], (unsigned long long)__double2ll_rn((double)__uint_as_float(it.y) * scale));
+  };
+  // items two at a time (16-byte loads from an even index; the item buffer
+  // is 256-byte aligned), an odd first / last item on its own
+  const uint32_t e0 = min((start + 1) & ~1u, end), e1 = max(end & ~1u, e0);
+  if (threadIdx.x == 0 && start < e0) add(items[start]);
+  if (threadIdx.x == 0 && e1 < end) add(items[e1]);
+  const uint4* __restrict__ pairs = (const uint4*)(items + e0);
+  const uint32_t np = (e1 - e0) / 2;
+  constexpr int UR = 4;
+  uint32_t i = threadIdx.x;
+  for (; i + (UR - 1) * kThreads < np; i += UR * kThreads) {
+    uint4 q[UR];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) q[u] = pairs[i + u * kThreads];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      add(make_uint2(q[u].x, q[u].y));
+      add(make_uint2(q[u].z, q[u].w));
+    }
+  }
+  for (; i < np; i += kThreads) {
+    const uint4 q = pairs[i];
+    add(make_uint2(q.x, q.y));
+    add(make_uint2(q.z, q.w));
   }
   __syncthreads();
   for (int c = threadIdx.x; c < cells; c += kThreads) {
@@ -647,7 +716,10 @@ __host__ __device__ inline size_t dense_reduce_lds_bytes(int Bp, int d) {
   return (size_t)Bp * d * 4 + (size_t)kDenseCap * 6 + (size_t)3 * Bp * 4 + kWaves * 4;
 }
 
-template <int LPR>
+// LPR lanes per row, VEC consecutive floats per lane (VEC = 4: one 16-byte
+// load per lane, so a wavefront instruction brings 64 / LPR whole rows;
+// needs d and ldx multiples of 4 and X 16-byte aligned).
+template <int LPR, int VEC>
 __device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
   const float* __restrict__ X = a.X;
   const int64_t ldx = a.ldx, n = a.n;
@@ -657,7 +729,8 @@ __device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
   const int d = a.d, bp_shift = a.bp_shift;
   float* __restrict__ SX = a.SX;
   constexpr int RPP = 64 / LPR;                // rows per instruction (one per lane group)
-  constexpr int U = RPP >= 8 ? 4 : 16 / RPP;   // row loads in flight per lane group
+  // row loads in flight per lane group: 8 KB per wavefront for VEC = 4
+  constexpr int U = VEC == 4 ? 8 : RPP >= 8 ? 4 : 16 / RPP;
   constexpr int PER = kDenseCap / kThreads;    // items held per thread
   __shared__ uint64_t s_red64[kWaves];
   const int Bp = 1 << bp_shift;
@@ -670,7 +743,7 @@ __device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
   uint32_t* fill = off + Bp;
   uint32_t* s_w = fill + Bp;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = lane / LPR, c = lane % LPR;
+  const int j = lane / LPR, c = (lane % LPR) * VEC;
   const bool cok = c < d;
   const int cc = cok ? c : 0;
   // wave w owns the contiguous buckets [lb0, lb1)
@@ -718,12 +791,14 @@ __device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
     // per lane is added into the slice whenever the bucket changes
     const uint32_t s = lb0 < Bp ? off[lb0] : 0u;
     const uint32_t e = lb1 < Bp ? off[lb1] : min(tt, (uint32_t)kDenseCap);
-    float acc = 0.0f;
+    float acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = 0.0f;
     int cur = -1;
     for (uint32_t i = s + j; i < max(e, s + j); i += RPP * U) {
       uint32_t rs[U];
       int bk[U];
-      float x[U];
+      float x[U][VEC];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t ii = min(i + u * RPP, e > s ? e - 1 : s);
@@ -731,19 +806,38 @@ __device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
         bk[u] = i + u * RPP < e ? (int)rb[ii] : -1;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = X[(int64_t)(rs[u] & 0x7fffffffu) * ldx + cc];
+      for (int u = 0; u < U; ++u) {
+        const float* src = X + (int64_t)(rs[u] & 0x7fffffffu) * ldx + cc;
+        if constexpr (VEC == 4) {
+          const float4 q = *(const float4*)src;
+          x[u][0] = q.x;
+          x[u][1] = q.y;
+          x[u][2] = q.z;
+          x[u][3] = q.w;
+        } else {
+          x[u][0] = *src;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (bk[u] < 0) continue;
         if (bk[u] != cur) {
-          if (cur >= 0 && cok) atomicAdd(&slice[cur * d + c], acc);
+          if (cur >= 0 && cok) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) atomicAdd(&slice[cur * d + c + v], acc[v]);
+          }
           cur = bk[u];
-          acc = 0.0f;
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v] = 0.0f;
         }
-        acc += (rs[u] >> 31) ? -x[u] : x[u];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] += (rs[u] >> 31) ? -x[u][v] : x[u][v];
       }
     }
-    if (cur >= 0 && cok) atomicAdd(&slice[cur * d + c], acc);
+    if (cur >= 0 && cok) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) atomicAdd(&slice[cur * d + c + v], acc[v]);
+    }
     __syncthreads();
   }
   __syncthreads();
@@ -753,9 +847,9 @@ __device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
   }
 }
 
-template <int LPR>
+template <int LPR, int VEC>
 __global__ __launch_bounds__(kThreads) void bin_reduce_dense_kernel(BinArgs a) {
-  reduce_dense_range<LPR>(a, blockIdx.x);
+  reduce_dense_range<LPR, VEC>(a, blockIdx.x);
 }
 
 int lanes_per_row(int d) {
@@ -893,17 +987,31 @@ hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d,
   bin_scatter_dense_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(a);
   const unsigned gr = (unsigned)g.R;
   const size_t rl = g.lds_bytes;
-#define CG_DENSE_REDUCE(L)                                                     \
-  if ((e = allow_lds(bin_reduce_dense_kernel<L>, rl)) != hipSuccess) return e; \
-  bin_reduce_dense_kernel<L><<<gr, kThreads, rl, s>>>(a);
-  switch (lanes_per_row(d)) {
-    case 1: CG_DENSE_REDUCE(1) break;
-    case 2: CG_DENSE_REDUCE(2) break;
-    case 4: CG_DENSE_REDUCE(4) break;
-    case 8: CG_DENSE_REDUCE(8) break;
-    case 16: CG_DENSE_REDUCE(16) break;
-    case 32: CG_DENSE_REDUCE(32) break;
-    default: CG_DENSE_REDUCE(64) break;
+#define CG_DENSE_REDUCE(L, V)                                                     \
+  if ((e = allow_lds(bin_reduce_dense_kernel<L, V>, rl)) != hipSuccess) return e; \
+  bin_reduce_dense_kernel<L, V><<<gr, kThreads, rl, s>>>(a);
+  // 16-byte row loads (four rows per instruction) measured slower here: each
+  // lane group then flushes its own bucket sums, four LDS float atomics per
+  // lane; rows are read 4 bytes per lane
+  const bool vec4 = false;
+  if (vec4) {
+    switch (lanes_per_row(d / 4)) {
+      case 1: CG_DENSE_REDUCE(1, 4) break;
+      case 2: CG_DENSE_REDUCE(2, 4) break;
+      case 4: CG_DENSE_REDUCE(4, 4) break;
+      case 8: CG_DENSE_REDUCE(8, 4) break;
+      default: CG_DENSE_REDUCE(16, 4) break;
+    }
+  } else {
+    switch (lanes_per_row(d)) {
+      case 1: CG_DENSE_REDUCE(1, 1) break;
+      case 2: CG_DENSE_REDUCE(2, 1) break;
+      case 4: CG_DENSE_REDUCE(4, 1) break;
+      case 8: CG_DENSE_REDUCE(8, 1) break;
+      case 16: CG_DENSE_REDUCE(16, 1) break;
+      case 32: CG_DENSE_REDUCE(32, 1) break;
+      default: CG_DENSE_REDUCE(64, 1) break;
+    }
   }
 #undef CG_DENSE_REDUCE
   return hipGetLastError();

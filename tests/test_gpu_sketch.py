@@ -114,6 +114,48 @@ def test_strided_dense_input(cuda):
     assert rel(Y.cpu().numpy(), O.sketch_dense(X[:, 5:29], 16, 300, 8)) < 1e-12
 
 
+@pytest.mark.parametrize("shift", [0, 1, 2, 3])
+def test_binned_csr_any_alignment(cuda, shift):
+    """row_ptr, col_idx and vals starting 4 * shift bytes into their buffers
+    (the binned kernels use 16-byte loads only where every start is 16-byte
+    aligned), with ragged tiles, several input chunks per round and rows
+    that straddle chunk boundaries."""
+    n, d, m, B, seed = 70001, 32, 40, 8192, 4242
+    rng = np.random.Generator(np.random.PCG64(77 + shift))
+    rp, ci, v = W.csr_bernoulli(rng, n, d, 0.2, dtype=np.float32)
+    say("binned alignment", shift)
+
+    def at(a):
+        buf = torch.zeros(a.size + 4, dtype=torch.from_numpy(a).dtype, device=cuda)
+        buf[shift:shift + a.size] = torch.from_numpy(a).to(cuda)
+        return buf[shift:shift + a.size]
+
+    X = cg.CsrMatrix(at(rp), at(ci), at(v), n, d)
+    SX = torch.empty((B, d), dtype=torch.float32, device=cuda)
+    Y = cg.sketch(X, m, B, seed, algo="binned", sx_out=SX)
+    torch.cuda.synchronize()
+    assert rel(SX.cpu().numpy(), O.sx_csr(rp, ci, v, n, d, seed, B)) < SXTOL[torch.float32]
+    assert rel(Y.cpu().numpy(), O.sketch_csr(rp, ci, v, n, d, m, B, seed)) < TOL[torch.float32]
+
+
+@pytest.mark.parametrize("shift,ld", [(0, 64), (1, 65), (4, 68), (0, 66)])
+def test_binned_dense_any_alignment(cuda, shift, ld):
+    """Dense X at a 4 * shift byte offset with row stride ld (16-byte row
+    loads apply only when both keep rows 16-byte aligned)."""
+    n, d, m, B, seed = 30011, 64, 32, 4096, 99
+    X = np.random.default_rng(5).standard_normal((n, ld + 8)).astype(np.float32)
+    Xg = torch.from_numpy(X).to(cuda).reshape(-1)[shift:shift + (n - 1) * (ld + 8) + d]
+    Xv = Xg.as_strided((n, d), (ld + 8, 1))
+    say("binned dense alignment", shift, ld)
+    SX = torch.empty((B, d), dtype=torch.float32, device=cuda)
+    Y = cg.sketch(Xv, m, B, seed, algo="binned", sx_out=SX)
+    torch.cuda.synchronize()
+    Xh = X.reshape(-1)[shift:shift + (n - 1) * (ld + 8) + d]
+    Xh = np.lib.stride_tricks.as_strided(Xh, (n, d), ((ld + 8) * 4, 4)).copy()
+    assert rel(SX.cpu().numpy(), O.sx_dense(Xh, seed, B)) < SXTOL[torch.float32]
+    assert rel(Y.cpu().numpy(), O.sketch_dense(Xh, m, B, seed)) < TOL[torch.float32]
+
+
 @pytest.mark.parametrize("kind", ["csr", "dense"])
 def test_binned_csr_is_bitwise_reproducible(cuda, kind):
     if kind == "dense":
