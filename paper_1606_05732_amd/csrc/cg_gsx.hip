@@ -119,18 +119,25 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
 
   const int64_t kbeg = (bx * kWaves + wave) * kc;
   const int64_t kend = min(kbeg + (int64_t)kc, B);
+  int ccol[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) ccol[nb] = min(col[nb], d - 1);
   for (int64_t kb = kbeg; kb < kend; kb += 4) {
+    // loads and normals are computed unguarded at a clamped index and the
+    // values past the chunk or the columns zeroed afterwards (a guarded load
+    // would be waited for at the end of its branch)
     const int64_t b = kb + kq;
-    T g[4] = {T(0), T(0), T(0), T(0)};
+    const bool bok = b < kend;
+    const int64_t cb = bok ? b : kend - 1;
+    T g[4];
     T x[NB];
-    if (b < kend) {
-      box_muller(gauss_block((uint32_t)b, q, key.k0, key.k1), g);
+    box_muller(gauss_block((uint32_t)cb, q, key.k0, key.k1), g);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x[nb] = col[nb] < d ? SX[b * d + col[nb]] : T(0);
-    } else {
+    for (int nb = 0; nb < NB; ++nb) x[nb] = SX[cb * d + ccol[nb]];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x[nb] = T(0);
-    }
+    for (int t = 0; t < 4; ++t) g[t] = bok ? g[t] : T(0);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) x[nb] = bok && col[nb] < d ? x[nb] : T(0);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -161,19 +168,11 @@ __device__ __forceinline__ int fp8_block_exponent(float amax) {
   return f <= 0.875f ? E - 9 : E - 8;
 }
 
-__device__ __forceinline__ long pack_fp8x8(const float (&v)[8], float scale) {
-  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0] * scale, v[1] * scale, 0, false);
-  lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2] * scale, v[3] * scale, lo, true);
-  int hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4] * scale, v[5] * scale, 0, false);
-  hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6] * scale, v[7] * scale, hi, true);
-  return (long)(uint32_t)lo | ((long)(uint32_t)hi << 32);
-}
-
-__device__ __forceinline__ v8bf pack_bf16x8(const float (&v)[8]) {
-  v8bf r;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) r[e] = (__bf16)v[e];
-  return r;
+// Two FP32 values to OCP FP8 E4M3 (round to nearest even, saturating) in
+// the low (HI = false) or high byte pair of `old`.
+template <bool HI>
+__device__ __forceinline__ int cvt_fp8(float a, float b, int old) {
+  return __builtin_amdgcn_cvt_pk_fp8_f32(a, b, old, HI);
 }
 
 // Reduced-precision inputs: BF16 (round to nearest even) or FP8 E4M3 with
@@ -196,9 +195,12 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
-  int col[NB];
+  int col[NB], ccol[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) col[nb] = n0 + nb * 16 + p;
+  for (int nb = 0; nb < NB; ++nb) {
+    col[nb] = n0 + nb * 16 + p;
+    ccol[nb] = min(col[nb], d - 1);
+  }
 
   const int64_t kbeg = ((int64_t)blockIdx.x * kWaves + wave) * kc;
   const int64_t kend = min(kbeg + (int64_t)kc, B);
@@ -218,6 +220,8 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
       xscale = ldexpf(1.0f, -e);
       yscale = ldexpf(1.0f, e - 6);
     }
+    // FP8 block products are rescaled before they join the accumulator;
+    // BF16 needs no scale and accumulates directly
     v4f tmp[4][NB];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -226,47 +230,88 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
 #pragma unroll
     for (int sub = 0; sub < KBLK / 32; ++sub) {
       const int64_t base = kb + sub * 32 + kq * 8;
-      float g[4][8];
-      float x[NB][8];
+      // operands packed as they are produced, two columns of B at a time;
+      // loads and normals unguarded at clamped indices, values past the
+      // chunk or the columns zeroed
+      int glo[4] = {0, 0, 0, 0}, ghi[4] = {0, 0, 0, 0};
+      int xlo[NB], xhi[NB];
+      v8bf gb[4], xb[NB];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t b = base + e;
-        float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (b < kend) box_muller(gauss_block((uint32_t)b, q, key.k0, key.k1), z);
+      for (int nb = 0; nb < NB; ++nb) xlo[nb] = xhi[nb] = 0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) g[t][e] = z[t];
+      for (int e = 0; e < 8; e += 2) {
+        const int64_t b0 = base + e, b1 = b0 + 1;
+        const bool ok0 = b0 < kend, ok1 = b1 < kend;
+        const int64_t c0 = ok0 ? b0 : kend - 1, c1 = ok1 ? b1 : kend - 1;
+        float z0[4], z1[4], x0[NB], x1[NB];
+        box_muller(gauss_block((uint32_t)c0, q, key.k0, key.k1), z0);
+        box_muller(gauss_block((uint32_t)c1, q, key.k0, key.k1), z1);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          x[nb][e] = (b < kend && col[nb] < d) ? SX[b * d + col[nb]] : 0.0f;
+        for (int nb = 0; nb < NB; ++nb) {
+          x0[nb] = SX[c0 * d + ccol[nb]];
+          x1[nb] = SX[c1 * d + ccol[nb]];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          z0[t] = ok0 ? z0[t] : 0.0f;
+          z1[t] = ok1 ? z1[t] : 0.0f;
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          x0[nb] = ok0 && col[nb] < d ? x0[nb] : 0.0f;
+          x1[nb] = ok1 && col[nb] < d ? x1[nb] : 0.0f;
+        }
+        if constexpr (FP8) {
+          // columns e, e + 1 go to byte pair (e / 2) % 2 of word e / 4
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            int& w = e < 4 ? glo[t] : ghi[t];
+            w = (e & 2) ? cvt_fp8<true>(z0[t] * 64.0f, z1[t] * 64.0f, w)
+                        : cvt_fp8<false>(z0[t] * 64.0f, z1[t] * 64.0f, w);
+          }
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            int& w = e < 4 ? xlo[nb] : xhi[nb];
+            w = (e & 2) ? cvt_fp8<true>(x0[nb] * xscale, x1[nb] * xscale, w)
+                        : cvt_fp8<false>(x0[nb] * xscale, x1[nb] * xscale, w);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            gb[t][e] = (__bf16)z0[t];
+            gb[t][e + 1] = (__bf16)z1[t];
+          }
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            xb[nb][e] = (__bf16)x0[nb];
+            xb[nb][e + 1] = (__bf16)x1[nb];
+          }
+        }
       }
       if constexpr (FP8) {
-        long xa[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) xa[nb] = pack_fp8x8(x[nb], xscale);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const long ga = pack_fp8x8(g[t], 64.0f);
+          const long ga = (long)(uint32_t)glo[t] | ((long)(uint32_t)ghi[t] << 32);
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            tmp[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ga, xa[nb], tmp[t][nb], 0, 0, 0);
+          for (int nb = 0; nb < NB; ++nb) {
+            const long xa = (long)(uint32_t)xlo[nb] | ((long)(uint32_t)xhi[nb] << 32);
+            tmp[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ga, xa, tmp[t][nb], 0, 0, 0);
+          }
         }
       } else {
-        v8bf xa[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) xa[nb] = pack_bf16x8(x[nb]);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const v8bf ga = pack_bf16x8(g[t]);
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
-            tmp[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, xa[nb], tmp[t][nb], 0, 0, 0);
-        }
+            acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb[t], xb[nb], acc[t][nb], 0, 0, 0);
       }
     }
+    if constexpr (FP8) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[t][nb] += tmp[t][nb] * yscale;
+        for (int nb = 0; nb < NB; ++nb) acc[t][nb] += tmp[t][nb] * yscale;
+    }
   }
   block_reduce_store<float, NB, v4f>(acc, red, wave, lane, group, n0, m, d,
                                      part + (size_t)blockIdx.x * m * d);

@@ -557,7 +557,9 @@ __global__ __launch_bounds__(kSThreads) void bin_scatter_csr_kernel(BinArgs a) {
   scatter_csr_tile(a, blockIdx.x);
 }
 
-// Dense.  A round is 512 rows, two per lane, one item per row.
+// Dense.  A round is 1024 rows, four per lane, one item per row (rounds
+// twice the CSR size: the per-round scan over the ranges costs as much as
+// the round's rows here).
 __device__ __forceinline__ void scatter_dense_tile(const BinArgs& a, int64_t tile) {
   const int64_t n = a.n;
   const uint32_t B = a.B;
@@ -570,18 +572,18 @@ __device__ __forceinline__ void scatter_dense_tile(const BinArgs& a, int64_t til
   const uint32_t bmask = (1u << bp_shift) - 1u;
   const int64_t t0 = tile * a.tile_rows;
   const int64_t t1 = min(t0 + a.tile_rows, n);
-  for (int64_t round = t0; round < t1; round += kRoundRows) {
-    const int64_t r = round + (int64_t)kRPT * threadIdx.x;
-    uint32_t hv[kRPT];
-    lane_hashes<kRPT>(r, t1, row_offset, B, key, hv);
+  for (int64_t round = t0; round < t1; round += kCRoundRows) {
+    const int64_t r = round + (int64_t)kCRPT * threadIdx.x;
+    uint32_t hv[kCRPT];
+    lane_hashes<kCRPT>(r, t1, row_offset, B, key, hv);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kRPT; ++j)
+    for (int j = 0; j < kCRPT; ++j)
       if (r + j < t1) atomicAdd(&L.r_cnt[hash_bucket(hv[j]) >> bp_shift], 1u);
     __syncthreads();
-    const uint32_t E = round_offsets(L, R);   // <= kRoundRows <= stage capacity
+    const uint32_t E = round_offsets(L, R);   // <= kCRoundRows <= stage capacity
 #pragma unroll
-    for (int j = 0; j < kRPT; ++j) {
+    for (int j = 0; j < kCRPT; ++j) {
       if (r + j < t1) {
         const uint32_t bucket = hash_bucket(hv[j]);
         const uint32_t p = bucket >> bp_shift;
@@ -942,7 +944,8 @@ BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B, int64_t tile_rows) {
   g.ok = g.R <= (csr ? kBinMaxRangesCsr : kBinMaxRangesDense) && d <= (csr ? kMaxD : 64) &&
          n < ((int64_t)1 << 31) && (int64_t)g.R * g.ntiles < ((int64_t)1 << 30) &&
          g.tile_rows % kRoundRows == 0 && g.tile_rows <= ((int64_t)1 << 24) &&
-         scatter_lds_bytes(g.R, csr) <= 160 * 1024 && stage_cap(g.R, csr) >= kRoundRows;
+         scatter_lds_bytes(g.R, csr) <= 160 * 1024 &&
+         stage_cap(g.R, csr) >= (csr ? kRoundRows : kCRoundRows);
   return g;
 }
 
