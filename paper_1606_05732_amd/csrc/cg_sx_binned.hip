@@ -71,7 +71,7 @@ constexpr int kMinStage = 1024;                // smallest output stage (items)
 constexpr int kDenseCap = 8192;                // items sorted per dense reduce pass
 
 static_assert(kTileRows % kRoundRows == 0, "tiles hold whole rounds");
-static_assert(kInCap % (4 * kSThreads) == 0, "input chunk is whole 16-byte steps per thread");
+static_assert(kInCap == 4 * kSThreads, "an entry-parallel chunk is four entries per thread");
 static_assert(kRPT == 2 || kRPT == 4, "rows per thread: 2 or 4");
 constexpr int kCRPT = 4;                       // count kernel: rows per thread per round
 constexpr int kCRoundRows = kCRPT * kSThreads;
@@ -285,6 +285,11 @@ struct ScatterLds {
   uint2* stage;
   uint2* in;
   int32_t* rpw;     // kSWaves windows of kRpWin words, aliasing `in`
+  // entry-parallel chunks (CSR, aliasing `in`): per-row packed hash and
+  // slot base of the round's rows, and the row marks of a chunk's entries
+  uint32_t* row_h;  // kRoundRows
+  uint32_t* row_s;  // kRoundRows
+  int32_t* marks;   // kInCap
   uint32_t *g_base, *g_next, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
   uint2* fl;        // R: (window slot of stage index 0, window end) for the flush
   uint32_t* s_w;    // kSWaves
@@ -295,6 +300,11 @@ __host__ __device__ inline size_t scatter_shared_bytes(bool csr) {
   const size_t in = (size_t)kInCap * 8, win = (size_t)kSWaves * kRpWin * 4;
   return csr ? (in > win ? in : win) : 0;
 }
+
+static_assert((size_t)2 * kRoundRows * 4 + (size_t)kInCap * 4 <= (size_t)kInCap * 8,
+              "row arrays and marks fit in the input chunk's space");
+static_assert((size_t)kSWaves * kRpWin * 4 <= (size_t)2 * kRoundRows * 4,
+              "row_ptr windows stay clear of the marks");
 
 __host__ __device__ inline size_t scatter_fixed_bytes(int R, bool csr) {
   return scatter_shared_bytes(csr) + (size_t)9 * R * 4 + kSWaves * 4 + 8;
@@ -319,6 +329,9 @@ __device__ __forceinline__ ScatterLds carve_scatter(int R, bool csr) {
   p += (size_t)stage_cap(R, csr) * 8;
   L.in = (uint2*)p;
   L.rpw = (int32_t*)p;
+  L.row_h = (uint32_t*)p;
+  L.row_s = L.row_h + kRoundRows;
+  L.marks = (int32_t*)(L.row_s + kRoundRows);
   p += scatter_shared_bytes(csr);
   uint32_t* q = (uint32_t*)p;
   L.g_base = q;
@@ -431,6 +444,8 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int32_t* w = L.rpw + wave * kRpWin;
   load_windows(L, a.hist, a.tot, R, a.ntiles, (uint32_t)nnz, tile);
+  // no marks yet (the first round's barrier orders this before any use)
+  *(int4*)(L.marks + 4 * threadIdx.x) = make_int4(-1, -1, -1, -1);
   const uint32_t bmask = (1u << bp_shift) - 1u;
   const int64_t t0 = tile * a.tile_rows;
   const int64_t t1 = min(t0 + a.tile_rows, n);
@@ -469,33 +484,84 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
     const int32_t S0 = L.s_seg[0];
     const int32_t S1 = max(L.s_seg[1], S0);
     const int32_t A = vecx ? (S0 & ~3) : S0;
+    // the round's row hashes and slot bases, for the entry-parallel chunks
+    // (the barrier at the first chunk orders them before their readers)
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      L.row_h[kRPT * threadIdx.x + j] = hv[j];
+      L.row_s[kRPT * threadIdx.x + j] = sadj[j];
+    }
+    int32_t carry = -1;   // row of the entry just before the chunk
     for (int32_t c0 = A; c0 < S1; c0 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1)) {
       const int32_t c1 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1);
       if (c0 != A) __syncthreads();   // every lane is done with the previous chunk
       if (vecx && c0 + kInCap <= nnz) {
         // a whole chunk inside the arrays (uniform over the workgroup):
-        // thread t stages entries c0 + 4 t + 4 kSThreads u + (0 .. 3) with one
-        // unguarded 16-byte load of each array; entries outside [S0, S1) are
-        // staged but never read
-        constexpr int G = kInCap / (4 * kSThreads);
-        int4 cq[G];
-        float4 vq[G];
+        // thread t takes entries c0 + 4 t + (0 .. 3), loaded with one unguarded
+        // 16-byte load of each array.  An entry's row is found without a
+        // search: each row owner marks the position of its row's first entry
+        // (marks[] is all -1 otherwise), and a max-scan over the marks in
+        // entry order gives every entry the last row started at or before it.
+        const int32_t g = c0 + 4 * (int32_t)threadIdx.x;
+        const int4 cq = *(const int4*)(col_idx + g);
+        const float4 vq = *(const float4*)(vals + g);
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-          const int32_t g = c0 + 4 * ((int32_t)threadIdx.x + u * kSThreads);
-          cq[u] = *(const int4*)(col_idx + g);
-          vq[u] = *(const float4*)(vals + g);
-        }
-        uint4* in4 = (uint4*)L.in;
+        for (int j = 0; j < kRPT; ++j)
+          if (len[j] && rp[j] >= c0 && rp[j] < c0 + kInCap)
+            L.marks[rp[j] - c0] = kRPT * (int32_t)threadIdx.x + j;
+        __syncthreads();
+        int4 mk = *(const int4*)(L.marks + 4 * threadIdx.x);
+        *(int4*)(L.marks + 4 * threadIdx.x) = make_int4(-1, -1, -1, -1);   // clean for the next chunk
+        mk.y = max(mk.y, mk.x);
+        mk.z = max(mk.z, mk.y);
+        mk.w = max(mk.w, mk.z);
+        // inclusive max-scan of the threads' last marks over the wavefront ...
+        int32_t incl = mk.w;
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-          const int32_t i2 = 2 * ((int32_t)threadIdx.x + u * kSThreads);
-          in4[i2] = make_uint4((uint32_t)cq[u].x, __float_as_uint(vq[u].x), (uint32_t)cq[u].y,
-                               __float_as_uint(vq[u].y));
-          in4[i2 + 1] = make_uint4((uint32_t)cq[u].z, __float_as_uint(vq[u].z), (uint32_t)cq[u].w,
-                                   __float_as_uint(vq[u].w));
+        for (int off = 1; off < 64; off <<= 1) {
+          const int32_t y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl = max(incl, y);
         }
-      } else {
+        int32_t before = __shfl_up(incl, 1, 64);
+        if (lane == 0) before = -1;
+        // ... and over the wavefronts before this one (and the chunk before)
+        if (lane == 63) L.s_w[wave] = (uint32_t)incl;
+        __syncthreads();
+        int32_t wcarry = carry, bmax = carry;
+#pragma unroll
+        for (int w2 = 0; w2 < kSWaves; ++w2) {
+          const int32_t t = (int32_t)L.s_w[w2];
+          if (w2 < wave) wcarry = max(wcarry, t);
+          bmax = max(bmax, t);
+        }
+        carry = bmax;
+        before = max(before, wcarry);
+        const int32_t rows4[4] = {max(mk.x, before), max(mk.y, before), max(mk.z, before),
+                                  max(mk.w, before)};
+        const int32_t cols4[4] = {cq.x, cq.y, cq.z, cq.w};
+        const float vals4[4] = {vq.x, vq.y, vq.z, vq.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int32_t k = g + i;
+          const int32_t row = rows4[i];
+          if (k < S0 || k >= S1 || row < 0) continue;
+          const uint32_t hj = L.row_h[row], sj = L.row_s[row];
+          const uint32_t bucket = hash_bucket(hj);
+          const uint32_t pr = bucket >> bp_shift;
+          const bool ok = (uint32_t)cols4[i] < (uint32_t)d;
+          const uint32_t cell = ok ? (bucket & bmask) * (uint32_t)d + (uint32_t)cols4[i] : 0u;
+          const float sv = ok ? (hash_negative(hj) ? -vals4[i] : vals4[i]) : 0.0f;
+          const uint32_t slot = sj + (uint32_t)k;
+          if (pr < (uint32_t)R) atomicMax(&L.r_max[pr], __float_as_uint(fabsf(sv)));
+          if (staged) {
+            if (slot < E) L.stage[slot] = make_uint2((pr << 16) | cell, __float_as_uint(sv));
+          } else if (pr < (uint32_t)R) {
+            if (slot < L.g_next[pr]) items[slot] = make_uint2(cell, __float_as_uint(sv));
+          }
+        }
+        continue;
+      }
+      {
         int32_t cc[kInCap / kSThreads];
         float vv[kInCap / kSThreads];
 #pragma unroll
@@ -511,6 +577,7 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
         }
       }
       __syncthreads();
+      // entries staged in LDS; every lane walks its own rows' entries
       const int32_t a = max(rp[0], c0), e = min(rp[kRPT], c1);
       for (int32_t k = a; k < e; ++k) {
         int j = 0;
