@@ -185,6 +185,18 @@ __device__ __forceinline__ void transpose_row_ptr(const RpLoad<RPT>& l, int32_t*
 template <int RPT>
 __device__ __forceinline__ void lane_hashes(int64_t r, int64_t t1, uint64_t row_offset, uint32_t B,
                                             Key key, uint32_t hv[RPT]) {
+  if constexpr (RPT == 2) {
+    // the lane pair (2i, 2i + 1) shares the Philox block(s) of its four rows;
+    // the odd lane takes the upper two words (rows at or past t1 are empty
+    // and their hashes unused)
+    const int odd = threadIdx.x & 1;
+    const int64_t rq = r - 2 * odd;
+    uint32_t h4[4] = {0u, 0u, 0u, 0u};
+    if (rq < t1) hash4(row_offset + (uint64_t)rq, B, key.k0, key.k1, h4);
+    hv[0] = odd ? h4[2] : h4[0];
+    hv[1] = odd ? h4[3] : h4[1];
+    return;
+  }
 #pragma unroll
   for (int g = 0; g < RPT; g += 4) {
     uint32_t h4[4] = {0u, 0u, 0u, 0u};
