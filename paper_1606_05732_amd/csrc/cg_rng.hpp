@@ -53,8 +53,12 @@ __device__ __forceinline__ uint32_t word_at(const Words4& w, int i) {
   return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
 }
 
-// Words for row quad q (tag 0).
+// Words for row quad q (tag 0).  The empty asm makes the key words opaque
+// here, so the round keys are formed with scalar adds at each call instead
+// of being hoisted out of the caller's loop into twenty scalar registers
+// (which the row-splitting kernels would spill).
 __device__ __forceinline__ Words4 hash_block(uint64_t q, uint32_t k0, uint32_t k1) {
+  asm volatile("" : "+s"(k0), "+s"(k1));
   return philox10(Words4{(uint32_t)q, (uint32_t)(q >> 32), 0u, 0u}, k0, k1);
 }
 

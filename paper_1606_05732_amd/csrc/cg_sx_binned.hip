@@ -13,7 +13,7 @@
 //     bases are prefix sums of the totals, which each consumer forms
 //     itself.  That gives every tile a private window in each range's item
 //     list, which bin_scatter_* fills.  A scatter workgroup takes its tile
-//     in rounds of 512 rows: it counts the round's items per range, places
+//     in rounds of 1024 rows: it counts the round's items per range, places
 //     them in LDS grouped by range, and writes each range's run with
 //     consecutive lanes on consecutive addresses.
 //  2. reduce: one workgroup per range accumulates its items in LDS and
@@ -22,10 +22,11 @@
 //
 // Global loads are lane-contiguous everywhere: a wavefront reads the
 // row_ptr values of its rows as one coalesced block (each lane loads its own
-// row starts with one 8- or 16-byte load), and a scatter round copies its whole
-// col_idx/vals segment into LDS with coalesced loads before any lane walks
-// its own rows.  (Lanes reading their own rows straight from memory touch
-// dozens of cache lines per load instruction and starve the address units.)
+// row starts with one 8- or 16-byte load), and a scatter round reads its whole
+// col_idx/vals segment in 16-byte pieces, consecutive lanes on consecutive
+// entries, and finds each entry's row afterwards.  (Lanes reading their own
+// rows straight from memory touch dozens of cache lines per load
+// instruction and starve the address units.)
 //
 // CSR items are (cell = local bucket * d + column, sigma v).  They are
 // summed as 64-bit fixed-point integers with ds_add_u64: the range's scale
@@ -60,18 +61,21 @@ constexpr int kThreads = 1024;                 // reduce kernels
 constexpr int kWaves = kThreads / 64;
 constexpr int kSThreads = 256;                 // count, scan and scatter kernels
 constexpr int kSWaves = kSThreads / 64;
-constexpr int kRPT = 2;                        // scatter: rows per thread per round
+constexpr int kRPT = 4;                        // scatter: rows per thread per round
 constexpr int kWaveRows = kRPT * 64;           // rows per wavefront per round
 constexpr int kRoundRows = kRPT * kSThreads;   // rows per workgroup round
 constexpr int kTileRows = 16384;               // rows per split tile
-constexpr int kInCap = 1024;                   // CSR entries per LDS input chunk
+constexpr int kInCap = 2048;                   // CSR entries per chunk
+constexpr int kEPT = kInCap / kSThreads;       // entries per thread of a chunk
 constexpr int kRpWin = kWaveRows + 4;          // LDS words of one row_ptr window
-constexpr size_t kScatterLds = 26 * 1024;      // LDS target of a scatter workgroup (6 per CU)
+// LDS target of a scatter workgroup: CSR 40 KiB (4 per CU), dense 26 KiB (6 per CU)
+constexpr size_t kScatterLdsCsr = 40 * 1024;
+constexpr size_t kScatterLdsDense = 26 * 1024;
 constexpr int kMinStage = 1024;                // smallest output stage (items)
 constexpr int kDenseCap = 8192;                // items sorted per dense reduce pass
 
 static_assert(kTileRows % kRoundRows == 0, "tiles hold whole rounds");
-static_assert(kInCap == 4 * kSThreads, "an entry-parallel chunk is four entries per thread");
+static_assert(kEPT % 4 == 0, "an entry-parallel chunk is whole 16-byte groups per thread");
 static_assert(kRPT == 2 || kRPT == 4, "rows per thread: 2 or 4");
 constexpr int kCRPT = 4;                       // count kernel: rows per thread per round
 constexpr int kCRoundRows = kCRPT * kSThreads;
@@ -88,31 +92,62 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ---------------------------------------------------------- wavefront scans
+// Inclusive scans over the 64 lanes of a wavefront on DPP lane moves (no
+// LDS round trip): shifts by 1, 2, 4 and 8 lanes inside each row of 16,
+// then rows 1 and 3 take lane 15 of the row before and rows 2 and 3 take
+// lane 31.  A lane without a source keeps `old`, the operation's identity.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr2, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr4, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr8, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppBcast15, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppBcast31, 0xc, 0xf, false);
+  return x;
+}
+
+__device__ __forceinline__ int32_t wave_incl_max(int32_t x) {
+  constexpr int32_t lo = INT32_MIN;
+  x = max(x, __builtin_amdgcn_update_dpp(lo, x, kDppRowShr1, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(lo, x, kDppRowShr2, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(lo, x, kDppRowShr4, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(lo, x, kDppRowShr8, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(lo, x, kDppBcast15, 0xa, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(lo, x, kDppBcast31, 0xc, 0xf, false));
+  return x;
+}
+
+// The value of lane l - 1 (lane 0 gets `first`) and of lane l + 1 (lane 63
+// gets `last`).
+__device__ __forceinline__ int32_t from_lane_below(int32_t x, int32_t first) {
+  return __builtin_amdgcn_update_dpp(first, x, kDppWaveShr1, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int32_t from_lane_above(int32_t x, int32_t last) {
+  return __builtin_amdgcn_update_dpp(last, x, kDppWaveShl1, 0xf, 0xf, false);
+}
+
 // Exclusive scan over the NT threads of the block; *total gets the sum.
+// Every wavefront reads all wavefront totals, so two barriers suffice (the
+// second frees s_w for the next call).
 template <int NT>
 __device__ uint32_t block_exscan(uint32_t v, uint32_t* s_w, uint32_t* total) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
+  const uint32_t x = wave_incl_add(v);
   if (lane == 63) s_w[wave] = x;
   __syncthreads();
-  if (wave == 0) {
-    uint32_t t = lane < NW ? s_w[lane] : 0u;
+  uint32_t before = 0u, all = 0u;
 #pragma unroll
-    for (int off = 1; off < NW; off <<= 1) {
-      const uint32_t y = __shfl_up(t, off, 64);
-      if (lane >= off) t += y;
-    }
-    if (lane < NW) s_w[lane] = t;
+  for (int w2 = 0; w2 < NW; ++w2) {
+    const uint32_t t = s_w[w2];
+    before += w2 < wave ? t : 0u;
+    all += t;
   }
-  __syncthreads();
-  const uint32_t before = wave ? s_w[wave - 1] : 0u;
-  *total = s_w[NW - 1];
+  *total = all;
   __syncthreads();
   return before + x - v;
 }
@@ -162,10 +197,9 @@ __device__ __forceinline__ void transpose_row_ptr(const RpLoad<RPT>& l, int32_t*
                                                   int32_t rp[RPT + 1]) {
   const int lane = threadIdx.x & 63;
   if (l.direct) {
-    const int32_t nxt = __shfl_down(l.v[0], 1, 64);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) rp[j] = l.v[j];
-    rp[RPT] = lane == 63 ? l.last : nxt;
+    rp[RPT] = from_lane_above(l.v[0], l.last);
   } else {
 #pragma unroll
     for (int j = 0; j < RPT; ++j) w[lane + 64 * j] = l.v[j];
@@ -302,31 +336,34 @@ struct ScatterLds {
   uint32_t* row_h;  // kRoundRows
   uint32_t* row_s;  // kRoundRows
   int32_t* marks;   // kInCap
-  uint32_t *g_base, *g_next, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
-  uint2* fl;        // R: (window slot of stage index 0, window end) for the flush
+  uint32_t *g_base, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
+  uint2* fl;        // R: (window slot of stage index 0, window end)
   uint32_t* s_w;    // kSWaves
   int32_t* s_seg;   // 2
 };
 
 __host__ __device__ inline size_t scatter_shared_bytes(bool csr) {
   const size_t in = (size_t)kInCap * 8, win = (size_t)kSWaves * kRpWin * 4;
-  return csr ? (in > win ? in : win) : 0;
+  const size_t rows = (size_t)2 * kRoundRows * 4 + (size_t)kInCap * 4;
+  return csr ? std::max(std::max(in, win), rows) : 0;
 }
 
-static_assert((size_t)2 * kRoundRows * 4 + (size_t)kInCap * 4 <= (size_t)kInCap * 8,
-              "row arrays and marks fit in the input chunk's space");
 static_assert((size_t)kSWaves * kRpWin * 4 <= (size_t)2 * kRoundRows * 4,
               "row_ptr windows stay clear of the marks");
 
 __host__ __device__ inline size_t scatter_fixed_bytes(int R, bool csr) {
-  return scatter_shared_bytes(csr) + (size_t)9 * R * 4 + kSWaves * 4 + 8;
+  return scatter_shared_bytes(csr) + (size_t)8 * R * 4 + kSWaves * 4 + 8;
+}
+
+__host__ __device__ constexpr size_t scatter_lds_target(bool csr) {
+  return csr ? kScatterLdsCsr : kScatterLdsDense;
 }
 
 // Items a scatter round may stage: what the LDS target leaves after the
 // fixed arrays, at least kMinStage.
 __host__ __device__ inline int stage_cap(int R, bool csr) {
-  const int64_t left = (int64_t)kScatterLds - (int64_t)scatter_fixed_bytes(R, csr);
-  const int cap = (int)((left > 0 ? left : 0) / 8) & ~255;
+  const int64_t left = (int64_t)scatter_lds_target(csr) - (int64_t)scatter_fixed_bytes(R, csr);
+  const int cap = (int)((left > 0 ? left : 0) / 8) & ~63;
   return cap < kMinStage ? kMinStage : cap;
 }
 
@@ -347,19 +384,18 @@ __device__ __forceinline__ ScatterLds carve_scatter(int R, bool csr) {
   p += scatter_shared_bytes(csr);
   uint32_t* q = (uint32_t*)p;
   L.g_base = q;
-  L.g_next = q + R;
-  L.g_run = q + 2 * R;
-  L.r_cnt = q + 3 * R;
-  L.r_off = q + 4 * R;
-  L.r_fill = q + 5 * R;
-  L.r_max = q + 6 * R;
-  L.fl = (uint2*)(q + 7 * R);
-  L.s_w = q + 9 * R;
+  L.g_run = q + R;
+  L.r_cnt = q + 2 * R;
+  L.r_off = q + 3 * R;
+  L.r_fill = q + 4 * R;
+  L.r_max = q + 5 * R;
+  L.fl = (uint2*)(q + 6 * R);
+  L.s_w = q + 8 * R;
   L.s_seg = (int32_t*)(L.s_w + kSWaves);
   return L;
 }
 
-// This tile's window [g_base, g_next) in every range's item list: range
+// This tile's window [g_base, fl.y) in every range's item list: range
 // bases are the prefix sums of the range totals, plus the tile's offset
 // inside the range (never past the item buffer, even if a malformed CSR
 // made the counts exceed nnz).  Also clears the per-range round state.
@@ -380,7 +416,7 @@ __device__ __forceinline__ void load_windows(const ScatterLds& L, const uint32_t
     const uint64_t lo = base + offs[(int64_t)p * ntiles + t];
     const uint64_t hi = base + (t + 1 < ntiles ? offs[(int64_t)p * ntiles + t + 1] : tp);
     L.g_base[p] = (uint32_t)min(lo, (uint64_t)total);
-    L.g_next[p] = (uint32_t)min(hi, (uint64_t)total);
+    L.fl[p] = make_uint2(0u, (uint32_t)min(hi, (uint64_t)total));
     L.g_run[p] = 0;
     L.r_cnt[p] = 0;
     L.r_fill[p] = 0;
@@ -403,7 +439,7 @@ __device__ __forceinline__ uint32_t round_offsets(const ScatterLds& L, int R) {
     const int p = b + k;
     if (p < R) {
       L.r_off[p] = run;
-      L.fl[p] = make_uint2(L.g_base[p] + L.g_run[p] - run, L.g_next[p]);
+      L.fl[p].x = L.g_base[p] + L.g_run[p] - run;
       run += L.r_cnt[p];
     }
   }
@@ -434,11 +470,33 @@ __device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t
   }
 }
 
-// CSR.  A round is 512 rows, two consecutive rows per lane.  The lanes
+// kEPT consecutive entries from k (a multiple of 4, 16-byte aligned
+// arrays, all in bounds) with 16-byte loads.
+__device__ __forceinline__ void load_entries(const int32_t* __restrict__ col_idx,
+                                             const float* __restrict__ vals, int32_t k,
+                                             int32_t cc[kEPT], float vv[kEPT]) {
+#pragma unroll
+  for (int u = 0; u < kEPT; u += 4) {
+    const int4 c = *(const int4*)(col_idx + k + u);
+    const float4 v = *(const float4*)(vals + k + u);
+    cc[u] = c.x;
+    cc[u + 1] = c.y;
+    cc[u + 2] = c.z;
+    cc[u + 3] = c.w;
+    vv[u] = v.x;
+    vv[u + 1] = v.y;
+    vv[u + 2] = v.z;
+    vv[u + 3] = v.w;
+  }
+}
+
+// CSR.  A round is 1024 rows, four consecutive rows per lane.  The lanes
 // count their rows' entries per range and reserve slots per row; the
-// round's entries -- one contiguous segment of col_idx/vals -- are copied
-// into LDS in chunks of kInCap with coalesced loads, and every lane then
-// walks its own rows' entries there and stages the items.
+// round's entries -- one contiguous segment of col_idx/vals -- are then
+// taken in chunks of kInCap, kEPT consecutive entries per thread, and
+// staged by range.  Without 16-byte alignment (or at the arrays' end) a
+// chunk is copied into LDS instead and every lane walks its own rows'
+// entries there.
 __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile) {
   const int32_t* __restrict__ row_ptr = a.row_ptr;
   const int32_t* __restrict__ col_idx = a.col_idx;
@@ -457,19 +515,41 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
   int32_t* w = L.rpw + wave * kRpWin;
   load_windows(L, a.hist, a.tot, R, a.ntiles, (uint32_t)nnz, tile);
   // no marks yet (the first round's barrier orders this before any use)
-  *(int4*)(L.marks + 4 * threadIdx.x) = make_int4(-1, -1, -1, -1);
+#pragma unroll
+  for (int u = 0; u < kEPT; u += 4)
+    *(int4*)(L.marks + kEPT * threadIdx.x + u) = make_int4(-1, -1, -1, -1);
   const uint32_t bmask = (1u << bp_shift) - 1u;
   const int64_t t0 = tile * a.tile_rows;
   const int64_t t1 = min(t0 + a.tile_rows, n);
   const bool vec = ((uintptr_t)row_ptr & 15) == 0;
   // 16-byte loads of the entries: chunks then start at multiples of 4
   const bool vecx = (((uintptr_t)col_idx | (uintptr_t)vals) & 15) == 0;
+  // Software pipeline: a round's row starts are loaded during the round
+  // before, and its first chunk of entries is requested before the count
+  // and offset scans, so neither load's latency is waited out on its own.
+  RpLoad<kRPT> rl_next = load_row_ptr<kRPT>(row_ptr, t0 + (int64_t)kWaveRows * wave, t1, vec);
   for (int64_t round = t0; round < t1; round += kRoundRows) {
     const int64_t r0 = round + (int64_t)kWaveRows * wave;
-    const RpLoad<kRPT> rl = load_row_ptr<kRPT>(row_ptr, r0, t1, vec);
+    const RpLoad<kRPT> rl = rl_next;
+    rl_next = load_row_ptr<kRPT>(row_ptr, r0 + kRoundRows, t1, vec);   // clamped to t1 at the end
     uint32_t hv[kRPT];
     lane_hashes<kRPT>(r0 + kRPT * lane, t1, row_offset, B, key, hv);
+    // the round's first entry: thread 0's first row start, as transpose_row_ptr clamps it
+    if (threadIdx.x == 0) L.s_seg[0] = min(max(rl.v[0], 0), nnz);
     __syncthreads();   // the previous round's flush is done with the LDS state
+    const int32_t S0 = __builtin_amdgcn_readfirstlane(L.s_seg[0]);
+    const int32_t A = vecx ? (S0 & ~3) : S0;
+    // the first chunk's 16-byte loads (uniform; the chunk loop uses them
+    // when its first chunk takes the vector path, which is this condition)
+    const bool pre = vecx && A + kInCap <= nnz;
+    int32_t cc0[kEPT];
+    float vv0[kEPT];
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+      cc0[u] = 0;
+      vv0[u] = 0.f;
+    }
+    if (pre) load_entries(col_idx, vals, A + kEPT * (int32_t)threadIdx.x, cc0, vv0);
     int32_t rp[kRPT + 1];
     transpose_row_ptr<kRPT>(rl, w, nnz, rp);
     uint32_t len[kRPT];
@@ -478,7 +558,6 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
       len[j] = (uint32_t)(rp[j + 1] - rp[j]);   // zero for rows at or past t1
       if (len[j]) atomicAdd(&L.r_cnt[hash_bucket(hv[j]) >> bp_shift], len[j]);
     }
-    if (threadIdx.x == 0) L.s_seg[0] = rp[0];
     if (threadIdx.x == kSThreads - 1) L.s_seg[1] = rp[kRPT];
     __syncthreads();
     const uint32_t E = round_offsets(L, R);
@@ -493,9 +572,7 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
       sadj[j] = s0 - (uint32_t)rp[j];
       maxb[j] = 0u;
     }
-    const int32_t S0 = L.s_seg[0];
     const int32_t S1 = max(L.s_seg[1], S0);
-    const int32_t A = vecx ? (S0 & ~3) : S0;
     // the round's row hashes and slot bases, for the entry-parallel chunks
     // (the barrier at the first chunk orders them before their readers)
 #pragma unroll
@@ -509,33 +586,40 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
       if (c0 != A) __syncthreads();   // every lane is done with the previous chunk
       if (vecx && c0 + kInCap <= nnz) {
         // a whole chunk inside the arrays (uniform over the workgroup):
-        // thread t takes entries c0 + 4 t + (0 .. 3), loaded with one unguarded
-        // 16-byte load of each array.  An entry's row is found without a
+        // thread t takes entries c0 + kEPT t + (0 .. kEPT - 1), loaded with
+        // unguarded 16-byte loads.  An entry's row is found without a
         // search: each row owner marks the position of its row's first entry
         // (marks[] is all -1 otherwise), and a max-scan over the marks in
         // entry order gives every entry the last row started at or before it.
-        const int32_t g = c0 + 4 * (int32_t)threadIdx.x;
-        const int4 cq = *(const int4*)(col_idx + g);
-        const float4 vq = *(const float4*)(vals + g);
+        const int32_t g = c0 + kEPT * (int32_t)threadIdx.x;
+        int32_t cc[kEPT];
+        float vv[kEPT];
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+          cc[u] = cc0[u];
+          vv[u] = vv0[u];
+        }
+        if (c0 != A) load_entries(col_idx, vals, g, cc, vv);
 #pragma unroll
         for (int j = 0; j < kRPT; ++j)
           if (len[j] && rp[j] >= c0 && rp[j] < c0 + kInCap)
             L.marks[rp[j] - c0] = kRPT * (int32_t)threadIdx.x + j;
         __syncthreads();
-        int4 mk = *(const int4*)(L.marks + 4 * threadIdx.x);
-        *(int4*)(L.marks + 4 * threadIdx.x) = make_int4(-1, -1, -1, -1);   // clean for the next chunk
-        mk.y = max(mk.y, mk.x);
-        mk.z = max(mk.z, mk.y);
-        mk.w = max(mk.w, mk.z);
-        // inclusive max-scan of the threads' last marks over the wavefront ...
-        int32_t incl = mk.w;
+        int32_t mk[kEPT];
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const int32_t y = __shfl_up(incl, off, 64);
-          if (lane >= off) incl = max(incl, y);
+        for (int u = 0; u < kEPT; u += 4) {
+          const int4 m = *(const int4*)(L.marks + kEPT * threadIdx.x + u);
+          *(int4*)(L.marks + kEPT * threadIdx.x + u) = make_int4(-1, -1, -1, -1);   // clean for the next chunk
+          mk[u] = m.x;
+          mk[u + 1] = m.y;
+          mk[u + 2] = m.z;
+          mk[u + 3] = m.w;
         }
-        int32_t before = __shfl_up(incl, 1, 64);
-        if (lane == 0) before = -1;
+#pragma unroll
+        for (int u = 1; u < kEPT; ++u) mk[u] = max(mk[u], mk[u - 1]);
+        // inclusive max-scan of the threads' last marks over the wavefront ...
+        const int32_t incl = wave_incl_max(mk[kEPT - 1]);
+        int32_t before = from_lane_below(incl, -1);
         // ... and over the wavefronts before this one (and the chunk before)
         if (lane == 63) L.s_w[wave] = (uint32_t)incl;
         __syncthreads();
@@ -548,27 +632,25 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
         }
         carry = bmax;
         before = max(before, wcarry);
-        const int32_t rows4[4] = {max(mk.x, before), max(mk.y, before), max(mk.z, before),
-                                  max(mk.w, before)};
-        const int32_t cols4[4] = {cq.x, cq.y, cq.z, cq.w};
-        const float vals4[4] = {vq.x, vq.y, vq.z, vq.w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kEPT; ++i) {
           const int32_t k = g + i;
-          const int32_t row = rows4[i];
-          if (k < S0 || k >= S1 || row < 0) continue;
+          // (a mark left by a copied chunk -- only with decreasing row_ptr --
+          // is not a row index: bounded here)
+          const int32_t row = max(mk[i], before);
+          if (k < S0 || k >= S1 || (uint32_t)row >= (uint32_t)kRoundRows) continue;
           const uint32_t hj = L.row_h[row], sj = L.row_s[row];
           const uint32_t bucket = hash_bucket(hj);
           const uint32_t pr = bucket >> bp_shift;
-          const bool ok = (uint32_t)cols4[i] < (uint32_t)d;
-          const uint32_t cell = ok ? (bucket & bmask) * (uint32_t)d + (uint32_t)cols4[i] : 0u;
-          const float sv = ok ? (hash_negative(hj) ? -vals4[i] : vals4[i]) : 0.0f;
+          const bool ok = (uint32_t)cc[i] < (uint32_t)d;
+          const uint32_t cell = ok ? (bucket & bmask) * (uint32_t)d + (uint32_t)cc[i] : 0u;
+          const float sv = ok ? (hash_negative(hj) ? -vv[i] : vv[i]) : 0.0f;
           const uint32_t slot = sj + (uint32_t)k;
           if (pr < (uint32_t)R) atomicMax(&L.r_max[pr], __float_as_uint(fabsf(sv)));
           if (staged) {
             if (slot < E) L.stage[slot] = make_uint2((pr << 16) | cell, __float_as_uint(sv));
           } else if (pr < (uint32_t)R) {
-            if (slot < L.g_next[pr]) items[slot] = make_uint2(cell, __float_as_uint(sv));
+            if (slot < L.fl[pr].y) items[slot] = make_uint2(cell, __float_as_uint(sv));
           }
         }
         continue;
@@ -618,7 +700,7 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
           if (slot < E) L.stage[slot] = make_uint2((p << 16) | cell, __float_as_uint(sv));
         } else {
           // a round too large for the stage (long rows): direct stores
-          if (slot < L.g_next[p]) items[slot] = make_uint2(cell, __float_as_uint(sv));
+          if (slot < L.fl[p].y) items[slot] = make_uint2(cell, __float_as_uint(sv));
         }
       }
     }
@@ -632,7 +714,8 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
   for (int q = threadIdx.x; q < R; q += kSThreads) a.hmax[(int64_t)q * a.ntiles + tile] = L.r_max[q];
 }
 
-__global__ __launch_bounds__(kSThreads) void bin_scatter_csr_kernel(BinArgs a) {
+// four workgroups per CU (the LDS target's occupancy): at most 128 VGPRs
+__global__ __launch_bounds__(kSThreads, 4) void bin_scatter_csr_kernel(BinArgs a) {
   scatter_csr_tile(a, blockIdx.x);
 }
 
@@ -988,7 +1071,7 @@ __global__ __launch_bounds__(kSThreads) void bin_scan_batched(const BinArgs* __r
   scan_range(a, (int)((int64_t)blockIdx.x - first[i]));
 }
 
-__global__ __launch_bounds__(kSThreads) void bin_scatter_batched(const BinArgs* __restrict__ args,
+__global__ __launch_bounds__(kSThreads, 4) void bin_scatter_batched(const BinArgs* __restrict__ args,
                                                                  const int32_t* __restrict__ inst,
                                                                  const int32_t* __restrict__ first) {
   const int i = inst[blockIdx.x];
@@ -1123,10 +1206,10 @@ hipError_t launch_sx_binned_batched(const BinArgs* args, const int32_t* tile_ins
                                     const int32_t* tile_first, int64_t tiles,
                                     const int32_t* range_inst, const int32_t* range_first,
                                     int64_t ranges, int r_max, size_t reduce_lds, hipStream_t s) {
-  // every instance's scatter layout fits: scatter_lds_bytes(R) <= max(kScatterLds,
+  // every instance's scatter layout fits: scatter_lds_bytes(R) <= max(kScatterLdsCsr,
   // scatter_lds_bytes(r_max)) for R <= r_max (the stage only shrinks to its floor
   // as R grows); count_lds_bytes grows with R
-  const size_t sl = std::max(scatter_lds_bytes(r_max, true), kScatterLds);
+  const size_t sl = std::max(scatter_lds_bytes(r_max, true), kScatterLdsCsr);
   const size_t cl = count_lds_bytes(r_max);
   hipError_t e;
   if ((e = allow_lds(bin_count_batched, cl)) != hipSuccess) return e;
