@@ -168,7 +168,7 @@ struct RpLoad {
   bool direct;
 };
 
-template <int RPT>
+template <int RPT, bool NT = true>
 __device__ __forceinline__ RpLoad<RPT> load_row_ptr(const int32_t* __restrict__ row_ptr, int64_t r0,
                                                     int64_t t1, bool aligned) {
   static_assert(RPT == 2 || RPT == 4, "2 or 4 rows per lane");
@@ -179,7 +179,8 @@ __device__ __forceinline__ RpLoad<RPT> load_row_ptr(const int32_t* __restrict__ 
   l.direct = __builtin_amdgcn_readfirstlane((int)(aligned && r0 + 64 * RPT <= t1)) != 0;
   if (l.direct) {
     typedef int32_t vNi __attribute__((ext_vector_type(RPT)));
-    const vNi q = __builtin_nontemporal_load((const vNi*)(row_ptr + r0 + RPT * lane));
+    const vNi* src = (const vNi*)(row_ptr + r0 + RPT * lane);
+    const vNi q = NT ? __builtin_nontemporal_load(src) : *src;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) l.v[j] = q[j];
   } else {
@@ -471,14 +472,18 @@ __device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t
 }
 
 // kEPT consecutive entries from k (a multiple of 4, 16-byte aligned
-// arrays, all in bounds) with 16-byte loads.
+// arrays, all in bounds) with 16-byte loads.  Non-temporal: X is read once
+// here, and streaming it past the caches keeps the item list this kernel
+// writes in the last-level cache for the reduce that reads it next.
 __device__ __forceinline__ void load_entries(const int32_t* __restrict__ col_idx,
                                              const float* __restrict__ vals, int32_t k,
                                              int32_t cc[kEPT], float vv[kEPT]) {
+  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int u = 0; u < kEPT; u += 4) {
-    const int4 c = *(const int4*)(col_idx + k + u);
-    const float4 v = *(const float4*)(vals + k + u);
+    const i32x4 c = __builtin_nontemporal_load((const i32x4*)(col_idx + k + u));
+    const f32x4 v = __builtin_nontemporal_load((const f32x4*)(vals + k + u));
     cc[u] = c.x;
     cc[u + 1] = c.y;
     cc[u + 2] = c.z;
@@ -997,15 +1002,19 @@ __device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        // non-temporal: each row of X is read once, and streaming it past
+        // the caches keeps S X (written next, read by the contraction) and
+        // the item list in the last-level cache
         const float* src = X + (int64_t)(rs[u] & 0x7fffffffu) * ldx + cc;
         if constexpr (VEC == 4) {
-          const float4 q = *(const float4*)src;
+          typedef float f32x4 __attribute__((ext_vector_type(4)));
+          const f32x4 q = __builtin_nontemporal_load((const f32x4*)src);
           x[u][0] = q.x;
           x[u][1] = q.y;
           x[u][2] = q.z;
           x[u][3] = q.w;
         } else {
-          x[u][0] = *src;
+          x[u][0] = __builtin_nontemporal_load(src);
         }
       }
 #pragma unroll
