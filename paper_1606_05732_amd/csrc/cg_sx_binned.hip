@@ -326,8 +326,8 @@ __global__ __launch_bounds__(kSThreads) void bin_scan_kernel(BinArgs a) { scan_r
 // ------------------------------------------------------------------ scatter
 // LDS of the scatter kernels:
 //   stage (cap items) | input chunk (kInCap items) sharing its space with
-//   the row_ptr windows (CSR only; a round uses the windows first, then
-//   the chunk) | per-range arrays (7 R words) | block scan | segment
+//   the row_ptr windows and the entry-parallel row arrays and marks (CSR
+//   only) | per-range arrays (8 R words) | block scan | segment bounds
 struct ScatterLds {
   uint2* stage;
   uint2* in;
@@ -340,7 +340,7 @@ struct ScatterLds {
   uint32_t *g_base, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
   uint2* fl;        // R: (window slot of stage index 0, window end)
   uint32_t* s_w;    // kSWaves
-  int32_t* s_seg;   // 2
+  int32_t* s_seg;   // 4: round start, last lane's end, end from row_ptr, (pad)
 };
 
 __host__ __device__ inline size_t scatter_shared_bytes(bool csr) {
@@ -353,7 +353,7 @@ static_assert((size_t)kSWaves * kRpWin * 4 <= (size_t)2 * kRoundRows * 4,
               "row_ptr windows stay clear of the marks");
 
 __host__ __device__ inline size_t scatter_fixed_bytes(int R, bool csr) {
-  return scatter_shared_bytes(csr) + (size_t)8 * R * 4 + kSWaves * 4 + 8;
+  return scatter_shared_bytes(csr) + (size_t)8 * R * 4 + kSWaves * 4 + 16;
 }
 
 __host__ __device__ constexpr size_t scatter_lds_target(bool csr) {
@@ -451,7 +451,10 @@ __device__ __forceinline__ uint32_t round_offsets(const ScatterLds& L, int R) {
 // Write the round's staged items (grouped by range in stage[0 .. E)) to
 // their windows -- consecutive lanes on consecutive slots of a run -- and
 // advance each range's write cursor.  `swap` puts the stage's second word
-// first (dense items).
+// first (dense items).  No barrier between the two parts: after the
+// staging barrier nothing reads the round's counts or cursors again, the
+// stores read only the stage and fl, and the next round's first barrier
+// orders both parts before any reuse.
 __device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t E, bool swap,
                                             uint2* __restrict__ items) {
   for (uint32_t i = threadIdx.x; i < E; i += kSThreads) {
@@ -463,7 +466,6 @@ __device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t
     if (pos < f.y)
       items[pos] = swap ? make_uint2(it.y, it.x & 0xffffu) : make_uint2(it.x & 0xffffu, it.y);
   }
-  __syncthreads();
   for (int p = threadIdx.x; p < R; p += kSThreads) {
     L.g_run[p] += L.r_cnt[p];
     L.r_cnt[p] = 0;
@@ -472,18 +474,22 @@ __device__ __forceinline__ void flush_stage(const ScatterLds& L, int R, uint32_t
 }
 
 // kEPT consecutive entries from k (a multiple of 4, 16-byte aligned
-// arrays, all in bounds) with 16-byte loads.  Non-temporal: X is read once
+// arrays) with 16-byte loads.  A group of four starting past `lim` (the
+// last group the chunk needs; lim + 4 <= nnz) reloads group `lim` instead:
+// same cache line as a neighbour's load, so nothing past the chunk is
+// fetched, and its entries are never used.  Non-temporal: X is read once
 // here, and streaming it past the caches keeps the item list this kernel
 // writes in the last-level cache for the reduce that reads it next.
 __device__ __forceinline__ void load_entries(const int32_t* __restrict__ col_idx,
-                                             const float* __restrict__ vals, int32_t k,
+                                             const float* __restrict__ vals, int32_t k, int32_t lim,
                                              int32_t cc[kEPT], float vv[kEPT]) {
   typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
   typedef float f32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int u = 0; u < kEPT; u += 4) {
-    const i32x4 c = __builtin_nontemporal_load((const i32x4*)(col_idx + k + u));
-    const f32x4 v = __builtin_nontemporal_load((const f32x4*)(vals + k + u));
+    const int32_t g = min(k + u, lim);
+    const i32x4 c = __builtin_nontemporal_load((const i32x4*)(col_idx + g));
+    const f32x4 v = __builtin_nontemporal_load((const f32x4*)(vals + g));
     cc[u] = c.x;
     cc[u + 1] = c.y;
     cc[u + 2] = c.z;
@@ -533,20 +539,33 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
   // before, and its first chunk of entries is requested before the count
   // and offset scans, so neither load's latency is waited out on its own.
   RpLoad<kRPT> rl_next = load_row_ptr<kRPT>(row_ptr, t0 + (int64_t)kWaveRows * wave, t1, vec);
+  // thread 0 also carries the next round's end, row_ptr[round end]
+  int32_t end_next = 0;
+  if (threadIdx.x == 0) end_next = row_ptr[min(t0 + kRoundRows, t1)];
   for (int64_t round = t0; round < t1; round += kRoundRows) {
     const int64_t r0 = round + (int64_t)kWaveRows * wave;
     const RpLoad<kRPT> rl = rl_next;
     rl_next = load_row_ptr<kRPT>(row_ptr, r0 + kRoundRows, t1, vec);   // clamped to t1 at the end
+    const int32_t end_raw = end_next;
+    if (threadIdx.x == 0) end_next = row_ptr[min(round + 2 * kRoundRows, t1)];
     uint32_t hv[kRPT];
     lane_hashes<kRPT>(r0 + kRPT * lane, t1, row_offset, B, key, hv);
-    // the round's first entry: thread 0's first row start, as transpose_row_ptr clamps it
-    if (threadIdx.x == 0) L.s_seg[0] = min(max(rl.v[0], 0), nnz);
+    // the round's first entry (thread 0's first row start, as
+    // transpose_row_ptr clamps it) and its end (as the last lane finds it,
+    // for well-formed row_ptr)
+    if (threadIdx.x == 0) {
+      const int32_t s0 = min(max(rl.v[0], 0), nnz);
+      L.s_seg[0] = s0;
+      L.s_seg[2] = max(min(max(end_raw, 0), nnz), s0);
+    }
     __syncthreads();   // the previous round's flush is done with the LDS state
     const int32_t S0 = __builtin_amdgcn_readfirstlane(L.s_seg[0]);
+    const int32_t S1e = __builtin_amdgcn_readfirstlane(L.s_seg[2]);
     const int32_t A = vecx ? (S0 & ~3) : S0;
     // the first chunk's 16-byte loads (uniform; the chunk loop uses them
-    // when its first chunk takes the vector path, which is this condition)
-    const bool pre = vecx && A + kInCap <= nnz;
+    // for its first chunk, which takes the vector path exactly when `pre`)
+    const int32_t lim0 = (min(A + kInCap, S1e) - 1) & ~3;
+    const bool pre = vecx && S1e > A && lim0 + 4 <= nnz;
     int32_t cc0[kEPT];
     float vv0[kEPT];
 #pragma unroll
@@ -554,7 +573,7 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
       cc0[u] = 0;
       vv0[u] = 0.f;
     }
-    if (pre) load_entries(col_idx, vals, A + kEPT * (int32_t)threadIdx.x, cc0, vv0);
+    if (pre) load_entries(col_idx, vals, A + kEPT * (int32_t)threadIdx.x, lim0, cc0, vv0);
     int32_t rp[kRPT + 1];
     transpose_row_ptr<kRPT>(rl, w, nnz, rp);
     uint32_t len[kRPT];
@@ -589,10 +608,11 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
     for (int32_t c0 = A; c0 < S1; c0 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1)) {
       const int32_t c1 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1);
       if (c0 != A) __syncthreads();   // every lane is done with the previous chunk
-      if (vecx && c0 + kInCap <= nnz) {
-        // a whole chunk inside the arrays (uniform over the workgroup):
-        // thread t takes entries c0 + kEPT t + (0 .. kEPT - 1), loaded with
-        // unguarded 16-byte loads.  An entry's row is found without a
+      const int32_t lim = (c1 - 1) & ~3;
+      if (c0 == A ? pre : vecx && lim + 4 <= nnz) {
+        // a chunk whose 16-byte groups lie inside the arrays (uniform over
+        // the workgroup): thread t takes entries c0 + kEPT t + (0 .. kEPT - 1),
+        // loaded with unguarded (clamped) 16-byte loads.  An entry's row is found without a
         // search: each row owner marks the position of its row's first entry
         // (marks[] is all -1 otherwise), and a max-scan over the marks in
         // entry order gives every entry the last row started at or before it.
@@ -604,7 +624,7 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
           cc[u] = cc0[u];
           vv[u] = vv0[u];
         }
-        if (c0 != A) load_entries(col_idx, vals, g, cc, vv);
+        if (c0 != A) load_entries(col_idx, vals, g, lim, cc, vv);
 #pragma unroll
         for (int j = 0; j < kRPT; ++j)
           if (len[j] && rp[j] >= c0 && rp[j] < c0 + kInCap)
