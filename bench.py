@@ -94,20 +94,39 @@ class HipEvents:
 
 
 def timed_steps(plan, steps, warmup, ev):
-    """Run warmup + timed steps; returns wall ms/step and per-stage event
-    times (ms, averaged over the timed steps)."""
+    """Run warmup steps, then three timed passes of `steps` steps each:
+      1. no stage events: wall ms/step (every recorded event leaves the GPU
+         idle for about 6 us between the kernels it separates, so the
+         step time is taken without them);
+      2. events at the S X stage's two ends only: the stage's time per
+         launch, with nothing recorded inside it;
+      3. events at all five boundaries: the per-stage breakdown (each stage
+         then also carries an event's idle time).
+    Returns (wall ms/step, per-stage ms, total ms of pass 3, S X stage ms)."""
     import torch
     for _ in range(warmup):
         plan.run()
-    sets = [ev.create(5) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        plan.set_stage_events(sets[i])
+    for _ in range(steps):
         plan.run()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    plan.set_stage_events(None)
+
+    def event_pass(mask):
+        sets = [ev.create(5) for _ in range(steps)]
+        for i in range(steps):
+            plan.set_stage_events([h if keep else None for h, keep in zip(sets[i], mask)])
+            plan.run()
+        torch.cuda.synchronize()
+        plan.set_stage_events(None)
+        return sets
+
+    sets = event_pass([True, False, True, False, False])
+    sx_stage = sum(ev.ms(s[0], s[2]) for s in sets) / steps
+    for s in sets:
+        ev.destroy(s)
+    sets = event_pass([True] * 5)
     # stage events: [0, 1) the S X prologue (binned: count and scan; atomic:
     # zero fill), [1, 2) the rest of S X, [2, 3) G (S X), [3, 4) the split reduction
     names = ["sx_prologue", "sx", "gsx", "reduce"]
@@ -119,7 +138,7 @@ def timed_steps(plan, steps, warmup, ev):
         total += ev.ms(s[0], s[4]) / steps
     for s in sets:
         ev.destroy(s)
-    return wall, stage, total
+    return wall, stage, total, sx_stage
 
 
 def counters_traffic(kernel_launches_bytes):
@@ -167,7 +186,7 @@ def ladder(steps, warmup, ev):
     out = {"workload": w.name, "nnz": int(w.nnz)}
     for prec in ("native", "bf16", "fp8"):
         plan = cg.SketchPlan(X, w.m, w.B, w.seed, precision=prec)
-        wall, stage, total = timed_steps(plan, steps, warmup, ev)
+        wall, stage, total, _ = timed_steps(plan, steps, warmup, ev)
         err = O.rel_frobenius(plan.Y.cpu().numpy(), ref)
         flops = 2.0 * w.m * w.B * w.d
         out["fp32" if prec == "native" else prec] = {
@@ -283,14 +302,16 @@ def main():
                      torch.from_numpy(c.vals).cuda(), c.n, c.d)
     plan = cg.SketchPlan(X, w.m, w.B, w.seed, algo=args.algo)
     log(f"workload {w.name}: nnz {c.nnz}, workspace {plan.workspace_bytes/2**20:.1f} MiB")
-    wall, stage, total = timed_steps(plan, args.steps, args.warmup, ev)
+    wall, stage, total, sx_stage = timed_steps(plan, args.steps, args.warmup, ev)
     nnz = c.nnz
     sx_bytes = 8 * nnz + 4 * (c.n + 1) + 4 * w.B * c.d
-    # the whole S X stage (prologue + main part) against its algorithmic bytes
-    sx_s = (stage["sx_prologue"] + stage["sx"]) * 1e-3
+    # the whole S X stage (count, scan, scatter, reduce; timed with events at
+    # its two ends only) against its algorithmic bytes
+    sx_s = sx_stage * 1e-3
     achieved = sx_bytes / sx_s / 1e9
     gsx_flops = 2.0 * w.m * w.B * c.d
-    log(f"wall {wall:.4f} ms/step; events: sx prologue {stage['sx_prologue']*1e3:.1f} us, "
+    log(f"wall {wall:.4f} ms/step; S X stage {sx_stage*1e3:.1f} us; "
+        f"with all stage events: sx prologue {stage['sx_prologue']*1e3:.1f} us, "
         f"sx {stage['sx']*1e3:.1f} us, gsx {stage['gsx']*1e3:.1f} us, "
         f"reduce {stage['reduce']*1e3:.1f} us, total {total*1e3:.1f} us")
     result = {
@@ -316,6 +337,8 @@ def main():
                      "traffic": counters_traffic(sx_bytes),
                      "algorithmic_bytes_per_launch": sx_bytes,
                      "avg_launch_us": round(sx_s * 1e6, 2)},
+        # per-stage breakdown from a pass with an event at every stage
+        # boundary (each stage then carries one event's idle time)
         "stages_us": {k: round(v * 1e3, 2) for k, v in stage.items()},
         "gsx": {"avg_launch_us": round(stage["gsx"] * 1e3, 2),
                 "tflops": round(gsx_flops / (stage["gsx"] * 1e-3) / 1e12, 3),

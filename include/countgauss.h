@@ -118,7 +118,10 @@ typedef struct cg_opts {
   void* const* stage_events;/* optional host array of CG_STAGE_EVENTS
                                hipEvent_t created by the caller; forward
                                calls record them on the stream at the stage
-                               boundaries (see below); NULL = none          */
+                               boundaries (see below); NULL = none, and a
+                               NULL entry skips its boundary (each record
+                               leaves the GPU idle for a few microseconds
+                               between the kernels it separates)           */
 } cg_opts;
 
 /* Forward stage boundaries recorded into cg_opts.stage_events:

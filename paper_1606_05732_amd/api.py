@@ -239,7 +239,8 @@ class SketchPlan:
     current stream (no allocation), so it can sit in a timed loop.
 
     stage_events: optional list of CG_STAGE_EVENTS raw hipEvent_t handles
-    (ints) that the library records at its stage boundaries."""
+    (ints) that the library records at its stage boundaries; a None entry
+    skips its boundary."""
 
     def __init__(self, X, m, B, seed, precision="native", algo="auto", row_offset=0, kc=0,
                  keep_sx=False):
@@ -285,7 +286,7 @@ class SketchPlan:
             return
         if len(handles) != L.CG_STAGE_EVENTS:
             raise ValueError(f"need {L.CG_STAGE_EVENTS} event handles")
-        self._events = (ctypes.c_void_p * L.CG_STAGE_EVENTS)(*handles)
+        self._events = (ctypes.c_void_p * L.CG_STAGE_EVENTS)(*[h or None for h in handles])
         self.opts.stage_events = ctypes.cast(self._events, ctypes.c_void_p)
 
     def run(self):

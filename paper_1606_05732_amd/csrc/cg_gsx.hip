@@ -122,26 +122,50 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
   int ccol[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) ccol[nb] = min(col[nb], d - 1);
-  for (int64_t kb = kbeg; kb < kend; kb += 4) {
-    // loads and normals are computed unguarded at a clamped index and the
-    // values past the chunk or the columns zeroed afterwards (a guarded load
-    // would be waited for at the end of its branch)
-    const int64_t b = kb + kq;
-    const bool bok = b < kend;
-    const int64_t cb = bok ? b : kend - 1;
-    T g[4];
-    T x[NB];
-    box_muller(gauss_block((uint32_t)cb, q, key.k0, key.k1), g);
+  // Groups of KU steps of 4 columns (kc is a multiple of 4 KU).  A group's
+  // S X values are loaded one group ahead, so their latency hides behind
+  // the previous group's normals and MFMAs.  Loads and normals are taken
+  // unguarded at a clamped index and the values past the chunk or the
+  // columns zeroed afterwards (a guarded load would be waited for at the
+  // end of its branch).
+  constexpr int KU = 4;
+  auto load_group = [&](int64_t kg, T (&x)[KU][NB]) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) x[nb] = SX[cb * d + ccol[nb]];
+    for (int u = 0; u < KU; ++u) {
+      const int64_t b = kg + 4 * u + kq;
+      const int64_t cb = b < kend ? b : kend - 1;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) g[t] = bok ? g[t] : T(0);
+      for (int nb = 0; nb < NB; ++nb) x[u][nb] = SX[cb * d + ccol[nb]];
+    }
+  };
+  // (unconditional: indices clamp to kend - 1 >= 0, and the group after
+  // the last is a harmless reload)
+  T xn[KU][NB];
+  load_group(kbeg, xn);
+  for (int64_t kg = kbeg; kg < kend; kg += 4 * KU) {
+    T x[KU][NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) x[nb] = bok && col[nb] < d ? x[nb] : T(0);
+    for (int u = 0; u < KU; ++u)
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int nb = 0; nb < NB; ++nb) x[u][nb] = xn[u][nb];
+    load_group(kg + 4 * KU, xn);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(g[t], x[nb], acc[t][nb]);
+    for (int u = 0; u < KU; ++u) {
+      const int64_t b = kg + 4 * u + kq;
+      const bool bok = b < kend;
+      const int64_t cb = bok ? b : kend - 1;
+      T g[4];
+      box_muller(gauss_block((uint32_t)cb, q, key.k0, key.k1), g);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) g[t] = bok ? g[t] : T(0);
+      T xv[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) xv[nb] = bok && col[nb] < d ? x[u][nb] : T(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(g[t], xv[nb], acc[t][nb]);
+    }
   }
   block_reduce_store<T, NB, V>(acc, red, wave, lane, group, n0, m, d, part + (size_t)bx * m * d);
 }
@@ -157,6 +181,36 @@ __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
   return v;
+}
+
+// Largest |x| over x[0 .. cnt) (NaNs ignored), this lane's share: 16-byte
+// loads with eight in flight when x is 16-byte aligned, else 4-byte loads.
+__device__ __forceinline__ float block_amax(const float* __restrict__ x, int64_t cnt, int lane) {
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  float am[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int64_t tail = 0;
+  if (((uintptr_t)x & 15) == 0) {
+    const f32x4* x4 = (const f32x4*)x;
+    const int64_t n4 = cnt >> 2;
+    int64_t i = lane;
+    for (; i + 7 * 64 < n4; i += 8 * 64) {
+      f32x4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = x4[i + u * 64];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        am[u] = fmaxf(am[u], fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)),
+                                   fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
+    }
+    for (; i < n4; i += 64) {
+      const f32x4 v = x4[i];
+      am[0] = fmaxf(am[0], fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    tail = n4 << 2;
+  }
+  for (int64_t i = tail + lane; i < cnt; i += 64) am[1] = fmaxf(am[1], fabsf(x[i]));
+  return fmaxf(fmaxf(fmaxf(am[0], am[1]), fmaxf(am[2], am[3])),
+               fmaxf(fmaxf(am[4], am[5]), fmaxf(am[6], am[7])));
 }
 
 // Smallest e with amax <= 448 * 2^e, from amax's binary exponent
@@ -207,13 +261,10 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
   for (int64_t kb = kbeg; kb < kend; kb += KBLK) {
     float xscale = 1.0f, yscale = 1.0f;
     if constexpr (FP8) {
-      // block amax over rows [kb, kb + 128) and all d columns of S X
-      float amax = 0.0f;
+      // block amax over rows [kb, kb + 128) and all d columns of S X:
+      // 16-byte loads, eight in flight per lane, when the block is aligned
       const int64_t rows = min((int64_t)KBLK, kend - kb);
-      const int64_t cnt = rows * d;
-      const float* blk = SX + kb * d;
-      for (int64_t i = lane; i < cnt; i += 64) amax = fmaxf(amax, fabsf(blk[i]));
-      amax = wave_max(amax);
+      const float amax = wave_max(block_amax(SX + kb * d, rows * d, lane));
       // blocks with amax below 448 * 2^-100 keep the scale 2^100 so that
       // 2^-e stays finite in FP32
       const int e = max(fp8_block_exponent(amax), -100);
@@ -409,10 +460,14 @@ GsxPlan plan_gsx(int64_t m, int64_t B, int64_t d, Prec prec, int kc_request, siz
   const int gran = prec == Prec::FP8 ? 128 : prec == Prec::BF16 ? 32 : 16;
   int64_t kc = kc_request;
   if (kc <= 0) {
-    // about 4096 wavefronts (16 per CU) in flight over the whole product
-    const int64_t target = 4096;
+    // about 2048 wavefronts (8 per CU) over the whole product, and at least
+    // 64 columns each: fewer, longer chunks than that cost more in split
+    // partials (written and reduced) than they gain in parallelism, and
+    // longer ones leave CUs idle (measured at m = 64, d = 32 and 64)
+    const int64_t target = 2048;
     const int64_t units = (int64_t)pl.mgroups * pl.ngroups;
     kc = (B * units + target - 1) / target;
+    if (kc < 64) kc = 64;
     if (kc > 8192) kc = 8192;
   }
   kc = (kc + gran - 1) / gran * gran;

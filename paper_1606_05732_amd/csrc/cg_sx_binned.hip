@@ -59,7 +59,7 @@ namespace {
 
 constexpr int kThreads = 1024;                 // reduce kernels
 constexpr int kWaves = kThreads / 64;
-constexpr int kSThreads = 256;                 // count, scan and scatter kernels
+constexpr int kSThreads = 256;                 // scan and scatter kernels
 constexpr int kSWaves = kSThreads / 64;
 constexpr int kRPT = 4;                        // scatter: rows per thread per round
 constexpr int kWaveRows = kRPT * 64;           // rows per wavefront per round
@@ -78,6 +78,9 @@ static_assert(kTileRows % kRoundRows == 0, "tiles hold whole rounds");
 static_assert(kEPT % 4 == 0, "an entry-parallel chunk is whole 16-byte groups per thread");
 static_assert(kRPT == 2 || kRPT == 4, "rows per thread: 2 or 4");
 constexpr int kCRPT = 4;                       // count kernel: rows per thread per round
+constexpr int kCntThreads = 512;               // count kernel: threads per workgroup
+constexpr int kCntWaves = kCntThreads / 64;
+constexpr int kCntRoundRows = kCRPT * kCntThreads;
 constexpr int kCRoundRows = kCRPT * kSThreads;
 constexpr int kCRpWin = 64 * kCRPT + 4;
 static_assert(kTileRows % kCRoundRows == 0, "tiles hold whole count rounds");
@@ -256,13 +259,13 @@ __device__ __forceinline__ void count_tile(const BinArgs& a, int64_t tile) {
   uint32_t* s_cnt = (uint32_t*)dyn_lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int32_t* w = (int32_t*)(s_cnt + R) + wave * 2 * kCRpWin;
-  for (int i = threadIdx.x; i < R; i += kSThreads) s_cnt[i] = 0;
+  for (int i = threadIdx.x; i < R; i += kCntThreads) s_cnt[i] = 0;
   __syncthreads();
   const int64_t t0 = tile * a.tile_rows;
   const int64_t t1 = min(t0 + a.tile_rows, n);
   const bool vec = ((uintptr_t)row_ptr & 15) == 0;
-  for (int64_t round = t0; round < t1; round += 2 * kCRoundRows) {
-    const int64_t ra = round + (int64_t)64 * kCRPT * wave, rb = ra + kCRoundRows;
+  for (int64_t round = t0; round < t1; round += 2 * kCntRoundRows) {
+    const int64_t ra = round + (int64_t)64 * kCRPT * wave, rb = ra + kCntRoundRows;
     RpLoad<kCRPT> la, lb;
     if (CSR) {
       la = load_row_ptr<kCRPT>(row_ptr, ra, t1, vec);
@@ -285,11 +288,11 @@ __device__ __forceinline__ void count_tile(const BinArgs& a, int64_t tile) {
     }
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < R; p += kSThreads) a.hist[(int64_t)p * a.ntiles + tile] = s_cnt[p];
+  for (int p = threadIdx.x; p < R; p += kCntThreads) a.hist[(int64_t)p * a.ntiles + tile] = s_cnt[p];
 }
 
 template <bool CSR>
-__global__ __launch_bounds__(kSThreads) void bin_count_kernel(BinArgs a) {
+__global__ __launch_bounds__(kCntThreads) void bin_count_kernel(BinArgs a) {
   count_tile<CSR>(a, blockIdx.x);
 }
 
@@ -1079,12 +1082,12 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-size_t count_lds_bytes(int R) { return (size_t)R * 4 + (size_t)kSWaves * 2 * kCRpWin * 4; }
+size_t count_lds_bytes(int R) { return (size_t)R * 4 + (size_t)kCntWaves * 2 * kCRpWin * 4; }
 
 // ------------------------------------------------------------------ batched
 // One workgroup per work item of any instance: item -> instance from the
 // item table, local index = item - first item of that instance.
-__global__ __launch_bounds__(kSThreads) void bin_count_batched(const BinArgs* __restrict__ args,
+__global__ __launch_bounds__(kCntThreads) void bin_count_batched(const BinArgs* __restrict__ args,
                                                                const int32_t* __restrict__ inst,
                                                                const int32_t* __restrict__ first) {
   const int i = inst[blockIdx.x];
@@ -1176,9 +1179,9 @@ hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, 
   if ((e = allow_lds(bin_count_kernel<true>, cl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_scatter_csr_kernel, sl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_reduce_csr_kernel, g.lds_bytes)) != hipSuccess) return e;
-  bin_count_kernel<true><<<(unsigned)g.ntiles, kSThreads, cl, s>>>(a);
+  bin_count_kernel<true><<<(unsigned)g.ntiles, kCntThreads, cl, s>>>(a);
   bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(a);
-  if (events && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
+  if (events && events[1] && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
   bin_scatter_csr_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(a);
   bin_reduce_csr_kernel<<<(unsigned)g.R, kThreads, g.lds_bytes, s>>>(a);
   return hipGetLastError();
@@ -1195,9 +1198,9 @@ hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d,
   hipError_t e;
   if ((e = allow_lds(bin_count_kernel<false>, cl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_scatter_dense_kernel, sl)) != hipSuccess) return e;
-  bin_count_kernel<false><<<(unsigned)g.ntiles, kSThreads, cl, s>>>(a);
+  bin_count_kernel<false><<<(unsigned)g.ntiles, kCntThreads, cl, s>>>(a);
   bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(a);
-  if (events && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
+  if (events && events[1] && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
   bin_scatter_dense_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(a);
   const unsigned gr = (unsigned)g.R;
   const size_t rl = g.lds_bytes;
@@ -1244,7 +1247,7 @@ hipError_t launch_sx_binned_batched(const BinArgs* args, const int32_t* tile_ins
   if ((e = allow_lds(bin_count_batched, cl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_scatter_batched, sl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_reduce_batched, reduce_lds)) != hipSuccess) return e;
-  if (tiles > 0) bin_count_batched<<<(unsigned)tiles, kSThreads, cl, s>>>(args, tile_inst, tile_first);
+  if (tiles > 0) bin_count_batched<<<(unsigned)tiles, kCntThreads, cl, s>>>(args, tile_inst, tile_first);
   if (ranges > 0) bin_scan_batched<<<(unsigned)ranges, kSThreads, 0, s>>>(args, range_inst, range_first);
   if (tiles > 0) bin_scatter_batched<<<(unsigned)tiles, kSThreads, sl, s>>>(args, tile_inst, tile_first);
   if (ranges > 0)

@@ -221,6 +221,57 @@ def test_sorted_path_is_bitwise_reproducible(cuda, kind):
     assert rel(atomic.cpu().numpy(), outs[0].cpu().numpy()) < 1e-5
 
 
+@pytest.mark.parametrize("algo", ["binned", "atomic", "sorted"])
+def test_stage_events_any_subset(cuda, algo):
+    """Stage events may be given for any subset of the boundaries (None
+    skips one); the result does not depend on them (bit for bit where the
+    algorithm is reproducible; the atomic path's order varies), and the
+    recorded ones are ordered."""
+    import ctypes
+    rt = None
+    for name in ("libamdhip64.so.7", "libamdhip64.so"):
+        try:
+            rt = ctypes.CDLL(name)
+            break
+        except OSError:
+            continue
+    assert rt is not None, "HIP runtime library not found"
+    rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                       ctypes.c_void_p]
+    rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    rng = np.random.default_rng(14)
+    n, d, m, B, seed = 40000, 16, 32, 8192, 9
+    rp, ci, v = W.csr_bernoulli(rng, n, d, 0.1, dtype=np.float32, absolute=True)
+    X = csr_to_gpu(rp, ci, v, n, d, cuda)
+    plan = cg.SketchPlan(X, m, B, seed, algo=algo)
+    plan.run()
+    torch.cuda.synchronize()
+    ref = plan.Y.clone()
+    evs = []
+    for _ in range(5):
+        h = ctypes.c_void_p()
+        assert rt.hipEventCreate(ctypes.byref(h)) == 0
+        evs.append(h.value)
+    say("stage events", algo)
+    for mask in ([1, 0, 1, 0, 0], [0, 0, 0, 0, 1], [1, 1, 1, 1, 1], [0, 0, 0, 0, 0]):
+        plan.set_stage_events([h if k else None for h, k in zip(evs, mask)])
+        plan.run()
+        torch.cuda.synchronize()
+        if algo == "atomic":
+            assert rel(plan.Y.cpu().numpy(), ref.cpu().numpy()) < TOL[torch.float32]
+        else:
+            assert torch.equal(plan.Y, ref)
+    plan.set_stage_events(None)
+    t = ctypes.c_float()
+    for a, b in ((0, 1), (1, 2), (2, 3), (3, 4)):
+        assert rt.hipEventElapsedTime(ctypes.byref(t), ctypes.c_void_p(evs[a]),
+                                      ctypes.c_void_p(evs[b])) == 0
+        assert t.value >= 0.0
+    for h in evs:
+        rt.hipEventDestroy(ctypes.c_void_p(h))
+
+
 def test_workload1_full_size(cuda):
     """CSR n = 10^6, d = 10, density 1%, m = 20, B = 2000: FP64 and FP32."""
     w = W.workload1()
