@@ -134,9 +134,10 @@ __device__ __forceinline__ int32_t from_lane_above(int32_t x, int32_t last) {
 }
 
 // Exclusive scan over the NT threads of the block; *total gets the sum.
-// Every wavefront reads all wavefront totals, so two barriers suffice (the
-// second frees s_w for the next call).
-template <int NT>
+// Every wavefront reads all wavefront totals, so two barriers suffice; the
+// second frees s_w for the next call, and a caller whose next write of s_w
+// comes after another barrier anyway leaves it out (FREE = false).
+template <int NT, bool FREE = true>
 __device__ uint32_t block_exscan(uint32_t v, uint32_t* s_w, uint32_t* total) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -151,7 +152,7 @@ __device__ uint32_t block_exscan(uint32_t v, uint32_t* s_w, uint32_t* total) {
     all += t;
   }
   *total = all;
-  __syncthreads();
+  if (FREE) __syncthreads();
   return before + x - v;
 }
 
@@ -335,10 +336,10 @@ struct ScatterLds {
   uint2* stage;
   uint2* in;
   int32_t* rpw;     // kSWaves windows of kRpWin words, aliasing `in`
-  // entry-parallel chunks (CSR, aliasing `in`): per-row packed hash and
-  // slot base of the round's rows, and the row marks of a chunk's entries
-  uint32_t* row_h;  // kRoundRows
-  uint32_t* row_s;  // kRoundRows
+  // entry-parallel chunks (CSR, aliasing `in`): per row of the round its
+  // packed hash and slot base (one 8-byte record), and the row marks of a
+  // chunk's entries
+  uint2* row_hs;    // kRoundRows
   int32_t* marks;   // kInCap
   uint32_t *g_base, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
   uint2* fl;        // R: (window slot of stage index 0, window end)
@@ -382,9 +383,8 @@ __device__ __forceinline__ ScatterLds carve_scatter(int R, bool csr) {
   p += (size_t)stage_cap(R, csr) * 8;
   L.in = (uint2*)p;
   L.rpw = (int32_t*)p;
-  L.row_h = (uint32_t*)p;
-  L.row_s = L.row_h + kRoundRows;
-  L.marks = (int32_t*)(L.row_s + kRoundRows);
+  L.row_hs = (uint2*)p;
+  L.marks = (int32_t*)(L.row_hs + kRoundRows);
   p += scatter_shared_bytes(csr);
   uint32_t* q = (uint32_t*)p;
   L.g_base = q;
@@ -430,7 +430,8 @@ __device__ __forceinline__ void load_windows(const ScatterLds& L, const uint32_t
 }
 
 // Exclusive offsets of the round's per-range counts (each thread scans
-// ceil(R / kSThreads) consecutive ranges); returns the total.
+// ceil(R / kSThreads) consecutive ranges); returns the total.  The scan's
+// s_w is next written after this function's closing barrier.
 __device__ __forceinline__ uint32_t round_offsets(const ScatterLds& L, int R) {
   const int per = (R + kSThreads - 1) / kSThreads;
   const int b = (int)threadIdx.x * per;
@@ -438,7 +439,7 @@ __device__ __forceinline__ uint32_t round_offsets(const ScatterLds& L, int R) {
   for (int k = 0; k < per; ++k)
     if (b + k < R) local += L.r_cnt[b + k];
   uint32_t E;
-  uint32_t run = block_exscan<kSThreads>(local, L.s_w, &E);
+  uint32_t run = block_exscan<kSThreads, false>(local, L.s_w, &E);
   for (int k = 0; k < per; ++k) {
     const int p = b + k;
     if (p < R) {
@@ -586,6 +587,13 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
       if (len[j]) atomicAdd(&L.r_cnt[hash_bucket(hv[j]) >> bp_shift], len[j]);
     }
     if (threadIdx.x == kSThreads - 1) L.s_seg[1] = rp[kRPT];
+    // the first chunk's row marks (when it takes the vector path); the
+    // barriers of the count and offset scans order them before their reads
+    if (pre) {
+#pragma unroll
+      for (int j = 0; j < kRPT; ++j)
+        if (len[j] && rp[j] >= A && rp[j] < A + kInCap) L.marks[rp[j] - A] = kRPT * (int32_t)threadIdx.x + j;
+    }
     __syncthreads();
     const uint32_t E = round_offsets(L, R);
     const bool staged = E <= cap;
@@ -602,11 +610,10 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
     const int32_t S1 = max(L.s_seg[1], S0);
     // the round's row hashes and slot bases, for the entry-parallel chunks
     // (the barrier at the first chunk orders them before their readers)
+    static_assert(kRPT % 2 == 0, "row records are written two per 16-byte store");
 #pragma unroll
-    for (int j = 0; j < kRPT; ++j) {
-      L.row_h[kRPT * threadIdx.x + j] = hv[j];
-      L.row_s[kRPT * threadIdx.x + j] = sadj[j];
-    }
+    for (int j = 0; j < kRPT; j += 2)
+      *(uint4*)&L.row_hs[kRPT * threadIdx.x + j] = make_uint4(hv[j], sadj[j], hv[j + 1], sadj[j + 1]);
     int32_t carry = -1;   // row of the entry just before the chunk
     for (int32_t c0 = A; c0 < S1; c0 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1)) {
       const int32_t c1 = (int32_t)min((int64_t)c0 + kInCap, (int64_t)S1);
@@ -627,12 +634,14 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
           cc[u] = cc0[u];
           vv[u] = vv0[u];
         }
-        if (c0 != A) load_entries(col_idx, vals, g, lim, cc, vv);
+        if (c0 != A) {   // a later chunk: its marks (the first chunk's are written)
+          load_entries(col_idx, vals, g, lim, cc, vv);
 #pragma unroll
-        for (int j = 0; j < kRPT; ++j)
-          if (len[j] && rp[j] >= c0 && rp[j] < c0 + kInCap)
-            L.marks[rp[j] - c0] = kRPT * (int32_t)threadIdx.x + j;
-        __syncthreads();
+          for (int j = 0; j < kRPT; ++j)
+            if (len[j] && rp[j] >= c0 && rp[j] < c0 + kInCap)
+              L.marks[rp[j] - c0] = kRPT * (int32_t)threadIdx.x + j;
+          __syncthreads();
+        }
         int32_t mk[kEPT];
 #pragma unroll
         for (int u = 0; u < kEPT; u += 4) {
@@ -667,7 +676,8 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
           // is not a row index: bounded here)
           const int32_t row = max(mk[i], before);
           if (k < S0 || k >= S1 || (uint32_t)row >= (uint32_t)kRoundRows) continue;
-          const uint32_t hj = L.row_h[row], sj = L.row_s[row];
+          const uint2 rhs = L.row_hs[row];
+          const uint32_t hj = rhs.x, sj = rhs.y;
           const uint32_t bucket = hash_bucket(hj);
           const uint32_t pr = bucket >> bp_shift;
           const bool ok = (uint32_t)cc[i] < (uint32_t)d;
