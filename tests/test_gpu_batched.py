@@ -104,7 +104,8 @@ def test_other_tuning_tables(cuda, rows, kc):
 def test_stale_plan_is_rejected(cuda):
     g = _to_gpu(_instances(MIXED[:3]))
     plan = cg.BatchedSketch(g)
-    cg.set_tuning(None, [64] * 11)
+    _, kc = cg.get_tuning()
+    cg.set_tuning(None, [2 * k for k in kc])   # any table other than the one planned with
     with pytest.raises(cg.CountGaussError):
         plan.run()
 
