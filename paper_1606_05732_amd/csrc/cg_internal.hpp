@@ -69,7 +69,8 @@ struct BinGeom {
   bool ok = false;         // this path applies
 };
 constexpr int64_t kBinTileRows = 16384;   // default rows per tile (a multiple of 1024)
-// tile_rows = 0 picks kBinTileRows; otherwise a multiple of 1024.
+// tile_rows = 0 picks about n / 1024 rows (whole 1024-row rounds, at most
+// kBinTileRows); otherwise a multiple of 1024.
 BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B, int64_t tile_rows = 0);
 size_t binned_scratch_bytes(const BinGeom& g, int64_t count);
 

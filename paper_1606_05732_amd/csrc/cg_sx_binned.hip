@@ -1143,7 +1143,16 @@ BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B, int64_t tile_rows) {
   }
   g.bp_shift = shift;
   g.R = (int)((B + ((int64_t)1 << shift) - 1) >> shift);
-  g.tile_rows = tile_rows > 0 ? tile_rows : kBinTileRows;
+  if (tile_rows > 0) {
+    g.tile_rows = tile_rows;
+  } else {
+    // about 1024 tiles (four workgroups per CU), whole 1024-row rounds, at
+    // most kBinTileRows: a small X still fills the GPU (each tile's rounds
+    // run one after another in its workgroup)
+    const int64_t per = (n + 1023) / 1024;
+    g.tile_rows = std::min<int64_t>(std::max<int64_t>((per + kRoundRows - 1) / kRoundRows, 1) * kRoundRows,
+                                    kBinTileRows);
+  }
   g.ntiles = (n + g.tile_rows - 1) / g.tile_rows;
   g.ok = g.R <= (csr ? kBinMaxRangesCsr : kBinMaxRangesDense) && d <= (csr ? kMaxD : 64) &&
          n < ((int64_t)1 << 31) && (int64_t)g.R * g.ntiles < ((int64_t)1 << 30) &&
