@@ -18,6 +18,14 @@
 // every generated normal is used exactly once.  D element (4 kq + r, p)
 // of M block t is Y row 4 (16 group + 4 kq + r) + t, column p (FP64: the
 // D rows of a lane are kq + 4 r instead, see d_row).
+//
+// Half groups: when a 64-row group holds at most 32 rows of G (m <= 32,
+// or the last group), only lanes p < 8 own rows that exist.  Lanes
+// p >= 8 then generate, for the row quad of lane p - 8, the normals of the
+// next step's columns, and a lane move (p + 8 -> p) hands them down: every
+// lane draws one Philox block per two steps, and the MFMAs see the same
+// operands in the same order as in a full group (rows >= 32 zero), so the
+// result is bit for bit the same.
 #include "cg_internal.hpp"
 #include "cg_rng.hpp"
 
@@ -98,15 +106,36 @@ __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int 
 // Native precision (FP32 or FP64 inputs, same-type accumulation).  One
 // workgroup: split `bx` along B, 64-row group `group` of G, column group
 // `ng` of S X.
+// Lane p + 8's value in lane p of each 16-lane row (0 in lanes 8 .. 15):
+// DPP row_shl:8, no LDS round trip.
+__device__ __forceinline__ float from_lane_p8(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x108, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_lane_p8(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x108, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x108, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Whether this 64-row group of G holds at most 32 existing rows.
+__device__ __forceinline__ bool half_group(int m, int group) { return m - 64 * group <= 32; }
+
 template <typename T, int NB>
+constexpr int red_elems() {
+  return 3 * 16 * NB * 64;
+}
+
+// `red`: red_elems<T, NB>() elements of LDS for the cross-wavefront sum.
+// HALF: the group holds at most 32 rows of G (see the file comment).
+template <typename T, int NB, bool HALF>
 __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64_t B, int d, int m,
                                                  int kc, Key key, T* __restrict__ part, int64_t bx,
-                                                 int group, int ng) {
+                                                 int group, int ng, T* red) {
   using V = typename Vec4<T>::type;
-  __shared__ T red[3 * 16 * NB * 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = lane & 15, kq = lane >> 4;
-  const uint32_t q = (uint32_t)(16 * group + p);
+  // half groups: lanes p and p + 8 share a row quad, one step apart
+  const uint32_t q = (uint32_t)(16 * group + (HALF ? (p & 7) : p));
   const int n0 = ng * NB * 16;
   V acc[4][NB];
 #pragma unroll
@@ -149,22 +178,52 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) x[u][nb] = xn[u][nb];
     load_group(kg + 4 * KU, xn);
+    if constexpr (HALF) {
 #pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      const int64_t b = kg + 4 * u + kq;
-      const bool bok = b < kend;
-      const int64_t cb = bok ? b : kend - 1;
-      T g[4];
-      box_muller(gauss_block((uint32_t)cb, q, key.k0, key.k1), g);
+      for (int u = 0; u < KU; u += 2) {
+        // this lane's normals: step u (p < 8) or step u + 1 (p >= 8)
+        const int64_t bg = kg + 4 * (u + (p >> 3)) + kq;
+        const bool gok = bg < kend;
+        T g[4];
+        box_muller(gauss_block((uint32_t)(gok ? bg : kend - 1), q, key.k0, key.k1), g);
+        T a0[4], a1[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) g[t] = bok ? g[t] : T(0);
-      T xv[NB];
+        for (int t = 0; t < 4; ++t) {
+          g[t] = gok ? g[t] : T(0);
+          a0[t] = p < 8 ? g[t] : T(0);
+          a1[t] = from_lane_p8(g[t]);
+        }
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) xv[nb] = bok && col[nb] < d ? x[u][nb] : T(0);
+        for (int h = 0; h < 2; ++h) {
+          // S X rows of step u + h (this lane's K slot kq, as in a full group)
+          const bool bok = kg + 4 * (u + h) + kq < kend;
+          T xv[NB];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+          for (int nb = 0; nb < NB; ++nb) xv[nb] = bok && col[nb] < d ? x[u + h][nb] : T(0);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(g[t], xv[nb], acc[t][nb]);
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(h ? a1[t] : a0[t], xv[nb], acc[t][nb]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int64_t b = kg + 4 * u + kq;
+        const bool bok = b < kend;
+        const int64_t cb = bok ? b : kend - 1;
+        T g[4];
+        box_muller(gauss_block((uint32_t)cb, q, key.k0, key.k1), g);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) g[t] = bok ? g[t] : T(0);
+        T xv[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) xv[nb] = bok && col[nb] < d ? x[u][nb] : T(0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(g[t], xv[nb], acc[t][nb]);
+      }
     }
   }
   block_reduce_store<T, NB, V>(acc, red, wave, lane, group, n0, m, d, part + (size_t)bx * m * d);
@@ -174,7 +233,11 @@ template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restrict__ SX, int64_t B,
                                                               int d, int m, int kc, Key key,
                                                               T* __restrict__ part) {
-  gsx_native_block<T, NB>(SX, B, d, m, kc, key, part, blockIdx.x, blockIdx.y, blockIdx.z);
+  __shared__ T red[red_elems<T, NB>()];
+  if (half_group(m, (int)blockIdx.y))
+    gsx_native_block<T, NB, true>(SX, B, d, m, kc, key, part, blockIdx.x, blockIdx.y, blockIdx.z, red);
+  else
+    gsx_native_block<T, NB, false>(SX, B, d, m, kc, key, part, blockIdx.x, blockIdx.y, blockIdx.z, red);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -421,7 +484,11 @@ __global__ __launch_bounds__(kThreads) void gsx_batched_kernel(const GsxArgs* __
   j /= a.parts;
   const int group = (int)(j % a.mgroups);
   const int ng = (int)(j / a.mgroups);
-  gsx_native_block<float, 4>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng);
+  __shared__ float red[red_elems<float, 4>()];
+  if (half_group(a.m, group))
+    gsx_native_block<float, 4, true>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
+  else
+    gsx_native_block<float, 4, false>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
 }
 
 __global__ __launch_bounds__(64 * kRedWaves) void splitk_batched_kernel(

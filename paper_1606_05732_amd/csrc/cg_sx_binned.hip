@@ -247,7 +247,8 @@ __device__ __forceinline__ void lane_hashes(int64_t r, int64_t t1, uint64_t row_
 
 // ------------------------------------------------------------------ count
 // hist[p * ntiles + t] = items of tile t that fall in range p.  Two rounds
-// per iteration, so each wavefront has ten row_ptr loads in flight.
+// per iteration, so each wavefront has both rounds' row_ptr loads in flight
+// while it hashes their rows.
 template <bool CSR>
 __device__ __forceinline__ void count_tile(const BinArgs& a, int64_t tile) {
   const int32_t* __restrict__ row_ptr = a.row_ptr;
@@ -403,29 +404,42 @@ __device__ __forceinline__ ScatterLds carve_scatter(int R, bool csr) {
 // bases are the prefix sums of the range totals, plus the tile's offset
 // inside the range (never past the item buffer, even if a malformed CSR
 // made the counts exceed nnz).  Also clears the per-range round state.
+// (All of a thread's loads -- its ranges' totals and this tile's offsets in
+// them -- are issued before the scan over the totals.)
 __device__ __forceinline__ void load_windows(const ScatterLds& L, const uint32_t* __restrict__ offs,
                                              const uint32_t* __restrict__ tot, int R,
                                              int64_t ntiles, uint32_t total, int64_t t) {
-  const int per = (R + kSThreads - 1) / kSThreads;
+  constexpr int kMaxR = kBinMaxRangesCsr > kBinMaxRangesDense ? kBinMaxRangesCsr : kBinMaxRangesDense;
+  constexpr int kMaxPer = (kMaxR + kSThreads - 1) / kSThreads;
+  const int per = (R + kSThreads - 1) / kSThreads;   // <= kMaxPer: bin_geometry bounds R
   const int b = (int)threadIdx.x * per;
+  uint32_t tp[kMaxPer], lo[kMaxPer], hi[kMaxPer];
   uint32_t local = 0;
-  for (int k = 0; k < per; ++k)
-    if (b + k < R) local += tot[b + k];
+#pragma unroll
+  for (int k = 0; k < kMaxPer; ++k) {
+    const int p = b + k;
+    tp[k] = lo[k] = hi[k] = 0u;
+    if (k < per && p < R) {
+      tp[k] = tot[p];
+      lo[k] = offs[(int64_t)p * ntiles + t];
+      hi[k] = t + 1 < ntiles ? offs[(int64_t)p * ntiles + t + 1] : tp[k];
+    }
+    local += tp[k];
+  }
   uint32_t all;
   uint64_t base = block_exscan<kSThreads>(local, L.s_w, &all);
-  for (int k = 0; k < per; ++k) {
+#pragma unroll
+  for (int k = 0; k < kMaxPer; ++k) {
     const int p = b + k;
-    if (p >= R) break;
-    const uint32_t tp = tot[p];
-    const uint64_t lo = base + offs[(int64_t)p * ntiles + t];
-    const uint64_t hi = base + (t + 1 < ntiles ? offs[(int64_t)p * ntiles + t + 1] : tp);
-    L.g_base[p] = (uint32_t)min(lo, (uint64_t)total);
-    L.fl[p] = make_uint2(0u, (uint32_t)min(hi, (uint64_t)total));
-    L.g_run[p] = 0;
-    L.r_cnt[p] = 0;
-    L.r_fill[p] = 0;
-    L.r_max[p] = 0;
-    base += tp;
+    if (k < per && p < R) {
+      L.g_base[p] = (uint32_t)min(base + lo[k], (uint64_t)total);
+      L.fl[p] = make_uint2(0u, (uint32_t)min(base + hi[k], (uint64_t)total));
+      L.g_run[p] = 0;
+      L.r_cnt[p] = 0;
+      L.r_fill[p] = 0;
+      L.r_max[p] = 0;
+    }
+    base += tp[k];
   }
 }
 
@@ -803,18 +817,6 @@ __global__ __launch_bounds__(kSThreads) void bin_scatter_dense_kernel(BinArgs a)
 }
 
 // ------------------------------------------------------------------ reduce
-__device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* s_red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor(v, off, 64));
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  uint32_t r = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) r = max(r, s_red[w]);
-  __syncthreads();
-  return r;
-}
-
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s_red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -825,6 +827,43 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s_red) {
   for (int w = 0; w < kWaves; ++w) r += s_red[w];
   __syncthreads();
   return r;
+}
+
+// CSR range p: the largest |value| bits over its tiles (hm: hmax row p)
+// and its items [sum of tot[0 .. p), + tot[p]), clamped to the buffer.
+// All loads are issued first and both values reduced in one barrier round
+// (the barrier also orders LDS writes made before the call); s_red and
+// s_red64 are not reused after it.
+__device__ __forceinline__ void csr_range_prologue(const uint32_t* __restrict__ tot,
+                                                   const uint32_t* __restrict__ hm, int64_t ntiles,
+                                                   int p, uint32_t total, uint32_t* s_red,
+                                                   uint64_t* s_red64, uint32_t* amax,
+                                                   uint32_t* start, uint32_t* end) {
+  uint32_t mx = 0;
+  uint64_t s = 0;
+  for (int64_t t = threadIdx.x; t < ntiles; t += kThreads) mx = max(mx, hm[t]);
+  for (int q = threadIdx.x; q < p; q += kThreads) s += tot[q];
+  const uint32_t tp = tot[p];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = max(mx, (uint32_t)__shfl_xor(mx, off, 64));
+    s += __shfl_xor(s, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_red[threadIdx.x >> 6] = mx;
+    s_red64[threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  uint32_t r = 0;
+  uint64_t S = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    r = max(r, s_red[w]);
+    S += s_red64[w];
+  }
+  *amax = r;
+  *start = (uint32_t)min(S, (uint64_t)total);
+  *end = (uint32_t)min(max(S + tp, (uint64_t)*start), (uint64_t)total);
 }
 
 // Items of range p: [sum of tot[0 .. p), + tot[p]), clamped to the buffer.
@@ -851,11 +890,9 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p) {
   __shared__ uint64_t s_red64[kWaves];
   const int cells = (1 << bp_shift) * d;
   for (int i = threadIdx.x; i < cells; i += kThreads) s_acc[i] = 0ull;
-  uint32_t mx = 0;
-  for (int64_t t = threadIdx.x; t < ntiles; t += kThreads) mx = max(mx, hmax[(int64_t)p * ntiles + t]);
-  const uint32_t amax_bits = block_max_u32(mx, s_red);   // its barrier also orders the zero fill
-  uint32_t start, end;
-  range_of(tot, p, total, s_red64, &start, &end);
+  uint32_t amax_bits, start, end;   // (the prologue's barrier also orders the zero fill)
+  csr_range_prologue(tot, hmax + (int64_t)p * ntiles, ntiles, p, total, s_red, s_red64, &amax_bits,
+                     &start, &end);
   if (amax_bits >= 0x7f800000u) {
     // a NaN or an infinity in this range: float atomics keep IEEE semantics
     float* acc = (float*)s_acc;

@@ -105,6 +105,33 @@ def test_row_offset_chunks_add_up(cuda):
     assert rel(got.cpu().numpy(), ref2) < 1e-12
 
 
+# A 64-row group of G holding at most 32 rows (m <= 32, or the last group
+# of a larger m) draws each Philox block once per two column steps and
+# moves half of the normals across lanes.  The MFMA operands for the rows
+# that exist are those of a full group, and G for m rows is the top rows of
+# G for more rows, so these rows must equal the first rows of a larger m
+# bit for bit (same split: kc is fixed, and both m have as many groups).
+# S X must be the same bits in both calls: the sorted path for dense X,
+# the binned path (fixed point) for CSR X.
+@pytest.mark.parametrize("m_small,m_big", [(32, 64), (1, 64), (17, 64), (96, 128), (70, 128)])
+@pytest.mark.parametrize("kind", ["dense64", "dense32", "csr32"])
+def test_half_group_rows_equal_full_group_rows(cuda, m_small, m_big, kind):
+    B, seed, kc = 5000, 41, 64   # B is not a multiple of the chunk: a ragged last chunk
+    if kind == "csr32":
+        rng = np.random.Generator(np.random.PCG64(9))
+        X = csr_to_gpu(*W.csr_bernoulli(rng, 6000, 64, 0.05, dtype=np.float32), 6000, 64)
+        algo = "binned"
+    else:
+        dt = torch.float64 if kind == "dense64" else torch.float32
+        X = torch.from_numpy(_dense_case(3000, 40, 8, dt)).to(cuda)
+        algo = "sorted"
+    say("half group", kind, m_small, m_big)
+    small = cg.sketch(X, m_small, B, seed, kc=kc, algo=algo)
+    big = cg.sketch(X, m_big, B, seed, kc=kc, algo=algo)
+    torch.cuda.synchronize()
+    assert torch.equal(small, big[:m_small])
+
+
 def test_strided_dense_input(cuda):
     X = np.random.default_rng(3).standard_normal((2000, 40))
     Xg = torch.from_numpy(X).to(cuda)[:, 5:29]        # row stride 40, d = 24
