@@ -72,11 +72,13 @@ constexpr int kRpWin = kWaveRows + 4;          // LDS words of one row_ptr windo
 constexpr size_t kScatterLdsCsr = 40 * 1024;
 constexpr size_t kScatterLdsDense = 26 * 1024;
 constexpr int kMinStage = 1024;                // smallest output stage (items)
+constexpr int kSparseRound = 512;              // CSR rounds with at most this many entries skip the stage
 constexpr int kDenseCap = 8192;                // items sorted per dense reduce pass
 
 static_assert(kTileRows % kRoundRows == 0, "tiles hold whole rounds");
 static_assert(kEPT % 4 == 0, "an entry-parallel chunk is whole 16-byte groups per thread");
 static_assert(kRPT == 2 || kRPT == 4, "rows per thread: 2 or 4");
+static_assert(kMinStage >= kRoundRows, "a sparse round keeps one record per row in the stage");
 constexpr int kCRPT = 4;                       // count kernel: rows per thread per round
 constexpr int kCntThreads = 512;               // count kernel: threads per workgroup
 constexpr int kCntWaves = kCntThreads / 64;
@@ -345,7 +347,8 @@ struct ScatterLds {
   uint32_t *g_base, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
   uint2* fl;        // R: (window slot of stage index 0, window end)
   uint32_t* s_w;    // kSWaves
-  int32_t* s_seg;   // 4: round start, last lane's end, end from row_ptr, (pad)
+  int32_t* s_seg;   // 8: (pad), last lane's end, (pad, pad), then per round parity
+                    // (round start, end from row_ptr)
 };
 
 __host__ __device__ inline size_t scatter_shared_bytes(bool csr) {
@@ -358,7 +361,7 @@ static_assert((size_t)kSWaves * kRpWin * 4 <= (size_t)2 * kRoundRows * 4,
               "row_ptr windows stay clear of the marks");
 
 __host__ __device__ inline size_t scatter_fixed_bytes(int R, bool csr) {
-  return scatter_shared_bytes(csr) + (size_t)8 * R * 4 + kSWaves * 4 + 16;
+  return scatter_shared_bytes(csr) + (size_t)8 * R * 4 + kSWaves * 4 + 32;
 }
 
 __host__ __device__ constexpr size_t scatter_lds_target(bool csr) {
@@ -570,15 +573,67 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
     lane_hashes<kRPT>(r0 + kRPT * lane, t1, row_offset, B, key, hv);
     // the round's first entry (thread 0's first row start, as
     // transpose_row_ptr clamps it) and its end (as the last lane finds it,
-    // for well-formed row_ptr)
+    // for well-formed row_ptr), in the slots of the round's parity: after
+    // a sparse round a wavefront may write the next round's bounds before
+    // another has read this round's
+    const int sb = 4 + 2 * (int)(((round - t0) / kRoundRows) & 1);
     if (threadIdx.x == 0) {
       const int32_t s0 = min(max(rl.v[0], 0), nnz);
-      L.s_seg[0] = s0;
-      L.s_seg[2] = max(min(max(end_raw, 0), nnz), s0);
+      L.s_seg[sb] = s0;
+      L.s_seg[sb + 1] = max(min(max(end_raw, 0), nnz), s0);
     }
     __syncthreads();   // the previous round's flush is done with the LDS state
-    const int32_t S0 = __builtin_amdgcn_readfirstlane(L.s_seg[0]);
-    const int32_t S1e = __builtin_amdgcn_readfirstlane(L.s_seg[2]);
+    const int32_t S0 = __builtin_amdgcn_readfirstlane(L.s_seg[sb]);
+    const int32_t S1e = __builtin_amdgcn_readfirstlane(L.s_seg[sb + 1]);
+    if (S1e - S0 <= kSparseRound) {
+      // A sparse round: no counts, scans, stage or flush, and no barrier
+      // beyond the one above.  Each lane reserves its rows' slots with one
+      // LDS atomic per nonempty row and keeps a record per row (packed
+      // hash, slot of entry 0) in its wavefront's part of the stage, and
+      // its row starts in its wavefront's row_ptr window.  The wavefront's
+      // entries -- one contiguous segment -- are then taken 64 at a time;
+      // each finds its row by binary search over the starts and is stored
+      // straight to its window.  The order of items inside a range does
+      // not change the fixed-point sums.  Only wavefront-private LDS is
+      // written besides the range cursors and maxima (atomics), and the
+      // next round's barrier orders those.
+      int32_t rp[kRPT + 1];
+      transpose_row_ptr<kRPT>(rl, w, nnz, rp);
+      uint2* rec = L.stage + wave * kWaveRows;
+#pragma unroll
+      for (int j = 0; j < kRPT; ++j) {
+        const uint32_t len = (uint32_t)(rp[j + 1] - rp[j]);
+        const uint32_t pr = hash_bucket(hv[j]) >> bp_shift;
+        const uint32_t s0 = len ? L.g_base[pr] + atomicAdd(&L.g_run[pr], len) : 0u;
+        rec[kRPT * lane + j] = make_uint2(hv[j], s0 - (uint32_t)rp[j]);
+        w[kRPT * lane + j] = rp[j];
+      }
+      const int32_t first = __builtin_amdgcn_readfirstlane(rp[0]);
+      const int32_t last = __builtin_amdgcn_readlane(rp[kRPT], 63);
+      wave_sync();
+      for (int32_t k = first + lane; k < last; k += 64) {
+        // the last of the wavefront's rows that starts at or before k
+        int lo = 0, hi = kWaveRows - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (w[mid] <= k) lo = mid;
+          else hi = mid - 1;
+        }
+        const uint2 r = rec[lo];
+        const uint32_t bucket = hash_bucket(r.x);
+        const uint32_t pr = bucket >> bp_shift;
+        const uint32_t c = (uint32_t)col_idx[k];
+        const float v = vals[k];
+        const bool ok = c < (uint32_t)d;
+        const uint32_t cell = ok ? (bucket & bmask) * (uint32_t)d + c : 0u;
+        const float sv = ok ? (hash_negative(r.x) ? -v : v) : 0.0f;
+        const uint32_t slot = r.y + (uint32_t)k;
+        atomicMax(&L.r_max[pr], __float_as_uint(fabsf(sv)));
+        if (slot < L.fl[pr].y) items[slot] = make_uint2(cell, __float_as_uint(sv));
+      }
+      wave_sync();
+      continue;
+    }
     const int32_t A = vecx ? (S0 & ~3) : S0;
     // the first chunk's 16-byte loads (uniform; the chunk loop uses them
     // for its first chunk, which takes the vector path exactly when `pre`)

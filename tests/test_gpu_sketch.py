@@ -202,6 +202,51 @@ def test_binned_csr_is_bitwise_reproducible(cuda, kind):
     assert rel(sxs[0].cpu().numpy(), O.sx_csr(rp, ci, v, n, d, seed, B)) < 2e-7
 
 
+def _mixed_density_csr(rng, n, d, block, dense_p, sparse_p, long_rows):
+    """CSR whose 1024-row blocks alternate between dense_p and sparse_p
+    density, plus the given rows made (almost) full: rounds of both kinds
+    in one tile, and long rows inside otherwise sparse rounds."""
+    rows = []
+    for b0 in range(0, n, block):
+        nb = min(block, n - b0)
+        p = dense_p if (b0 // block) % 2 == 0 else sparse_p
+        mask = rng.random((nb, d)) < p
+        rows.extend(mask)
+    mask = np.array(rows)
+    for r in long_rows:
+        mask[r, :] = rng.random(d) < 0.8
+    row_ptr = np.concatenate([[0], np.cumsum(mask.sum(axis=1))]).astype(np.int32)
+    col_idx = np.nonzero(mask)[1].astype(np.int32)
+    vals = rng.standard_normal(col_idx.size).astype(np.float32)
+    return row_ptr, col_idx, vals
+
+
+@pytest.mark.parametrize("d,long_rows", [(32, []), (500, [1024 + 7, 5 * 1024 + 1023, 9 * 1024]),
+                                         (64, [3 * 1024 + 500])])
+def test_binned_csr_sparse_and_dense_rounds(cuda, d, long_rows):
+    """Rounds with few entries take the scatter's sparse path (no stage);
+    tiles that mix both kinds of round, and long rows inside sparse rounds
+    (their entries spread over the wavefront), must give the oracle's S X,
+    the same bits on every run."""
+    rng = np.random.default_rng(31 + d)
+    n, m, B, seed = 40000, 24, 20000, 5
+    # about 2048 entries in a dense round (staged for d = 32 and 64, direct
+    # stores for d = 500, whose 1250 ranges leave a small stage), about 50
+    # in a sparse one
+    rp, ci, v = _mixed_density_csr(rng, n, d, 1024, 2.0 / d, 0.05 / d, long_rows)
+    X = csr_to_gpu(rp, ci, v, n, d, cuda)
+    say("binned sparse/dense rounds", d, len(ci))
+    sxs = []
+    for _ in range(3):
+        SX = torch.empty((B, d), dtype=torch.float32, device=cuda)
+        Y = cg.sketch(X, m, B, seed, algo="binned", sx_out=SX)
+        sxs.append(SX)
+    torch.cuda.synchronize()
+    assert torch.equal(sxs[0], sxs[1]) and torch.equal(sxs[0], sxs[2])
+    assert rel(sxs[0].cpu().numpy(), O.sx_csr(rp, ci, v, n, d, seed, B)) < SXTOL[torch.float32]
+    assert rel(Y.cpu().numpy(), O.sketch_csr(rp, ci, v, n, d, m, B, seed)) < TOL[torch.float32]
+
+
 @pytest.mark.parametrize("algo", ["atomic", "binned", "sorted"])
 def test_nan_and_inf_reach_their_bucket(cuda, algo):
     rng = np.random.default_rng(13)
