@@ -76,9 +76,11 @@ extern "C" {
  * BF16/FP8) and reduce the split over B in a fixed order.                */
 
 /* ---- algorithm for S X ------------------------------------------------- */
-#define CG_SX_AUTO 0        /* library's choice: BINNED for FP32 data when
-                               its bucket ranges fit (d <= 64 for dense X),
-                               ATOMIC otherwise                            */
+#define CG_SX_AUTO 0        /* library's choice: for FP32 CSR data at native
+                               precision without sx_out, ROWS where its cost
+                               model puts it below the S X route; else
+                               BINNED for FP32 data when its bucket ranges
+                               fit (d <= 64 for dense X), ATOMIC otherwise */
 #define CG_SX_ATOMIC 1      /* one device-scope atomic add per stored entry;
                                summation order within a bucket varies from
                                run to run                                  */
@@ -92,6 +94,18 @@ extern "C" {
                                entries below max|x| * 2^-(61 - log2 count)
                                lose precision); dense rows are summed in FP32
                                (order varies from run to run)              */
+#define CG_SX_ROWS 4        /* FP32 CSR data, native precision, no sx_out:
+                               S X is not formed.  Y is accumulated as the
+                               sum over the nonempty rows r of
+                               sigma(r) G[:, h(r)] x_r^T -- the same product
+                               G (S X) (Section 1.1: S puts row r into
+                               column h(r) with sign sigma(r)) -- in FP32
+                               MFMA partials per 1024 to 8192 rows (more
+                               rows per partial for larger n), reduced in a
+                               fixed order (bitwise reproducible).  Draws m
+                               normals per nonempty row instead of per
+                               bucket: for X with few nonempty rows next to
+                               B (d^2 m buckets and sparse X)            */
 
 /* ---- workspace kinds --------------------------------------------------- */
 #define CG_KIND_CSR 0
@@ -217,7 +231,8 @@ typedef struct cg_instance {
   int32_t tiles;            /* S X work items (row tiles)                   */
   int32_t ranges;           /* bucket ranges of 2^bp_shift buckets          */
   int32_t bp_shift;
-  int32_t kc;               /* columns of G per contraction wavefront       */
+  int32_t kc;               /* columns of G per contraction wavefront
+                               (rows route: rows of X per wavefront)     */
   int32_t parts;            /* contraction splits along B (4 kc columns)    */
   int32_t gsx_items;        /* contraction work items                       */
   int32_t red_items;        /* split-reduction work items                   */
@@ -225,13 +240,17 @@ typedef struct cg_instance {
   int32_t first_range;
   int32_t first_gsx;
   int32_t first_red;
-  int32_t reserved;
+  int32_t route;            /* 0: S X then G (S X); 1: rows route (no S X,
+                               see CG_SX_ROWS): no tiles or ranges, and its
+                               parts split the rows, 4 kc per part       */
 } cg_instance;
 
 /*
- * Plan a batch: validate every instance, choose its tile shapes from the
- * tuning table (by the class ceil(log2 d) of its d) and fill the planning
- * fields of inst (host array of count entries, in/out).  *workspace_bytes
+ * Plan a batch: validate every instance, choose its route (the rows route
+ * where the cost model of CG_SX_AUTO puts it below the S X route) and its
+ * tile shapes from the tuning table (by the class ceil(log2 d) of its d),
+ * and fill the planning fields of inst (host array of count entries,
+ * in/out).  *workspace_bytes
  * receives the workspace cg_sketch_batched needs.  Host only; queues
  * nothing.  Errors: CG_EINVAL / CG_EUNSUPPORTED, the message naming the
  * instance (e.g. d too large for the binned S X, a NULL pointer).

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcountgau
 CG_OK, CG_EINVAL, CG_ENOSPACE, CG_EUNSUPPORTED, CG_EHIP = 0, 1, 2, 3, 4
 CG_DTYPE_F32, CG_DTYPE_F64 = 0, 1
 CG_PREC_NATIVE, CG_PREC_BF16, CG_PREC_FP8 = 0, 1, 2
-CG_SX_AUTO, CG_SX_ATOMIC, CG_SX_SORTED, CG_SX_BINNED = 0, 1, 2, 3
+CG_SX_AUTO, CG_SX_ATOMIC, CG_SX_SORTED, CG_SX_BINNED, CG_SX_ROWS = 0, 1, 2, 3, 4
 CG_KIND_CSR, CG_KIND_DENSE, CG_KIND_ADJOINT, CG_KIND_ADJOINT_CSR = 0, 1, 2, 3
 
 # Every function declared in include/countgauss.h.
@@ -68,7 +68,7 @@ class CgInstance(ctypes.Structure):
         ("first_range", ctypes.c_int32),
         ("first_gsx", ctypes.c_int32),
         ("first_red", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("route", ctypes.c_int32),
     ]
 
 

@@ -14,7 +14,7 @@ from . import _lib as L
 _PREC = {"native": L.CG_PREC_NATIVE, "fp32": L.CG_PREC_NATIVE, "fp64": L.CG_PREC_NATIVE,
          "bf16": L.CG_PREC_BF16, "fp8": L.CG_PREC_FP8}
 _ALGO = {"auto": L.CG_SX_AUTO, "atomic": L.CG_SX_ATOMIC, "sorted": L.CG_SX_SORTED,
-         "binned": L.CG_SX_BINNED}
+         "binned": L.CG_SX_BINNED, "rows": L.CG_SX_ROWS}
 
 
 @dataclass
@@ -83,9 +83,10 @@ def _as_csr(X):
 def sketch(X, m, B, seed, precision="native", algo="auto", row_offset=0, kc=0, sx_out=None):
     """Y = T X = G (S X) (m x d) for dense X (n x d, unit column stride) or
     CSR X (CsrMatrix or torch.sparse_csr).  precision: native (FP32/FP64),
-    bf16 or fp8 inputs to the G (S X) contraction.  algo: auto, atomic or
-    sorted (bitwise reproducible) S X.  sx_out: optional B x d tensor that
-    receives S X."""
+    bf16 or fp8 inputs to the G (S X) contraction.  algo: auto, atomic,
+    sorted (bitwise reproducible), binned S X, or rows (FP32 CSR, native
+    precision: no S X, Y summed over the nonempty rows).  sx_out: optional
+    B x d tensor that receives S X (not with rows)."""
     lib = L.load()
     prec = _PREC[precision]
     sx_algo = _ALGO[algo]
@@ -361,7 +362,7 @@ class BatchedSketch:
         """The planned fields of instance i (tile rows, tiles, ranges, kc, ...)."""
         c = self._table[i]
         return {k: getattr(c, k) for k in ("ws_off", "tile_rows", "tiles", "ranges", "bp_shift",
-                                           "kc", "parts", "gsx_items", "red_items")}
+                                           "kc", "parts", "gsx_items", "red_items", "route")}
 
     def run(self):
         lib = L.load()

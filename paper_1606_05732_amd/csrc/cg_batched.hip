@@ -134,19 +134,23 @@ int make_plan(const cg_instance* src, int32_t count, Plan* p) {
       return failf(CG_EINVAL, "instance %d: B = %lld outside [1, 2^31)", i, (long long)c.B);
     if (c.row_offset < 0)
       return failf(CG_EINVAL, "instance %d: row_offset %lld < 0", i, (long long)c.row_offset);
-    const int cls = d_class(c.d);
-    const BinGeom g = bin_geometry(true, c.n, (int)c.d, c.B, t.rows[cls]);
-    if (!g.ok)
-      return failf(CG_EUNSUPPORTED, "instance %d: binned S X does not apply (d = %lld, B = %lld)",
-                   i, (long long)c.d, (long long)c.B);
-    const int64_t kc = t.kc[cls];
-    const int64_t parts = (c.B + 4 * kc - 1) / (4 * kc);
     const int64_t mgroups = (c.m + 63) / 64, ngroups = (c.d + 63) / 64;
     const int64_t red = (c.m * c.d + 63) / 64;
-    c.tile_rows = g.tile_rows;
-    c.tiles = (int32_t)g.ntiles;
-    c.ranges = g.R;
-    c.bp_shift = g.bp_shift;
+    const bool rows = rows_route_pays(c.n, c.d, c.nnz, c.m, c.B);
+    const int cls = d_class(c.d);
+    const BinGeom g = rows ? BinGeom{} : bin_geometry(true, c.n, (int)c.d, c.B, t.rows[cls]);
+    if (!rows && !g.ok)
+      return failf(CG_EUNSUPPORTED, "instance %d: binned S X does not apply (d = %lld, B = %lld)",
+                   i, (long long)c.d, (long long)c.B);
+    const int64_t kc = rows ? kBatchedRowsPerWave : t.kc[cls];   // rows route: rows per wavefront
+    const int64_t parts = rows ? rows_parts(c.n, (int)kc) : (c.B + 4 * kc - 1) / (4 * kc);
+    if (parts * mgroups * ngroups >= (1LL << 31) - 1)
+      return failf(CG_EUNSUPPORTED, "instance %d: too many contraction work items", i);
+    c.route = rows ? 1 : 0;
+    c.tile_rows = rows ? 0 : g.tile_rows;
+    c.tiles = rows ? 0 : (int32_t)g.ntiles;
+    c.ranges = rows ? 0 : g.R;
+    c.bp_shift = rows ? 0 : g.bp_shift;
     c.kc = (int32_t)kc;
     c.parts = (int32_t)parts;
     c.gsx_items = (int32_t)(parts * mgroups * ngroups);
@@ -155,7 +159,6 @@ int make_plan(const cg_instance* src, int32_t count, Plan* p) {
     c.first_range = (int32_t)p->ranges;
     c.first_gsx = (int32_t)p->gsx;
     c.first_red = (int32_t)p->red;
-    c.reserved = 0;
     p->tiles += c.tiles;
     p->ranges += c.ranges;
     p->gsx += c.gsx_items;
@@ -163,9 +166,10 @@ int make_plan(const cg_instance* src, int32_t count, Plan* p) {
     if (p->tiles >= (1LL << 31) - 1 || p->ranges >= (1LL << 31) - 1 || p->gsx >= (1LL << 31) - 1 ||
         p->red >= (1LL << 31) - 1)
       return failf(CG_EUNSUPPORTED, "batch has more than 2^31 work items in one phase");
-    if (g.R > p->r_max) p->r_max = g.R;
-    if (g.lds_bytes > p->reduce_lds) p->reduce_lds = g.lds_bytes;
-    sizes[i] = instance_bytes(g.R, g.ntiles, c.nnz, c.B, c.d, parts, c.m);
+    if (!rows && g.R > p->r_max) p->r_max = g.R;
+    if (!rows && g.lds_bytes > p->reduce_lds) p->reduce_lds = g.lds_bytes;
+    sizes[i] = rows ? align256((size_t)(parts * c.m * c.d * 4))
+                    : instance_bytes(g.R, g.ntiles, c.nnz, c.B, c.d, parts, c.m);
   }
   p->header = header_layout(count, p->tiles, p->ranges, p->gsx, p->red);
   size_t off = p->header.bytes;
@@ -182,7 +186,7 @@ bool same_plan(const cg_instance& a, const cg_instance& b) {
          a.ranges == b.ranges && a.bp_shift == b.bp_shift && a.kc == b.kc && a.parts == b.parts &&
          a.gsx_items == b.gsx_items && a.red_items == b.red_items &&
          a.first_tile == b.first_tile && a.first_range == b.first_range &&
-         a.first_gsx == b.first_gsx && a.first_red == b.first_red;
+         a.first_gsx == b.first_gsx && a.first_red == b.first_red && a.route == b.route;
 }
 
 // One workgroup per instance: kernel arguments, first items and the
@@ -210,12 +214,13 @@ __global__ __launch_bounds__(256) void batched_setup_kernel(
     a.R = c.ranges;
     a.ntiles = c.tiles;
     a.tile_rows = c.tile_rows;
-    const size_t bin = bin_carve(base, c.ranges, c.tiles, c.nnz, &a);
-    a.SX = (float*)(base + bin);
+    // the rows route keeps only its partials (at base); no S X scratch
+    const size_t bin = c.route ? 0 : bin_carve(base, c.ranges, c.tiles, c.nnz, &a);
+    a.SX = c.route ? nullptr : (float*)(base + bin);
     bargs[i] = a;
     GsxArgs g{};
     g.SX = a.SX;
-    g.part = (float*)(base + bin + align256((size_t)(c.B * c.d * 4)));
+    g.part = c.route ? (float*)base : (float*)(base + bin + align256((size_t)(c.B * c.d * 4)));
     g.Y = c.Y;
     g.B = c.B;
     g.d = (int32_t)c.d;
@@ -225,6 +230,13 @@ __global__ __launch_bounds__(256) void batched_setup_kernel(
     g.mgroups = (int32_t)((c.m + 63) / 64);
     g.ngroups = (int32_t)((c.d + 63) / 64);
     g.key = a.key;
+    g.row_ptr = c.row_ptr;
+    g.col_idx = c.col_idx;
+    g.vals = c.vals;
+    g.n = c.n;
+    g.row_offset = (uint64_t)c.row_offset;
+    g.nnz = (int32_t)c.nnz;
+    g.route = c.route;
     gargs[i] = g;
     firsts[i] = c.first_tile;
     firsts[count + i] = c.first_range;

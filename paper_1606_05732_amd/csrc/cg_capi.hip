@@ -72,7 +72,7 @@ int read_opts(const cg_opts* o, Opts* out) {
   out->events = o->stage_events;
   if (out->precision < CG_PREC_NATIVE || out->precision > CG_PREC_FP8)
     return fail(CG_EINVAL, "unknown precision %d", out->precision);
-  if (out->sx_algo < CG_SX_AUTO || out->sx_algo > CG_SX_BINNED)
+  if (out->sx_algo < CG_SX_AUTO || out->sx_algo > CG_SX_ROWS)
     return fail(CG_EINVAL, "unknown sx_algo %d", out->sx_algo);
   if (out->kc < 0 || out->kc % 16 != 0 || out->kc > (1 << 20))
     return fail(CG_EINVAL, "kc %d must be 0 or a positive multiple of 16 up to 2^20", out->kc);
@@ -103,17 +103,34 @@ int check_shape(int dtype, int64_t n, int64_t d, int64_t m, int64_t B, const Opt
   return CG_OK;
 }
 
-// The S X algorithm a call runs: AUTO resolves to BINNED for FP32 data
-// whose bucket ranges fit, else ATOMIC; BINNED asked for where it does not
-// apply is an error.
-int resolve_algo(int dtype, bool csr, int64_t n, int64_t d, int64_t B, int requested) {
+// The algorithm a call runs: AUTO resolves to ROWS for FP32 CSR data at
+// native precision without sx_out where the cost model favours it, else to
+// BINNED for FP32 data whose bucket ranges fit, else ATOMIC.  BINNED asked
+// for where it does not apply is -1, ROWS likewise -2 (errors).
+constexpr int kNoBinned = -1, kNoRows = -2;
+
+int resolve_algo(int dtype, bool csr, int64_t n, int64_t d, int64_t nnz, int64_t m, int64_t B,
+                 const Opts& o) {
+  const bool rows_ok = csr && dtype == CG_DTYPE_F32 && o.precision == CG_PREC_NATIVE && !o.sx_out;
+  if (o.sx_algo == CG_SX_ROWS) return rows_ok ? CG_SX_ROWS : kNoRows;
   const bool fits = dtype == CG_DTYPE_F32 && cg::bin_geometry(csr, n, (int)d, B).ok;
-  if (requested == CG_SX_AUTO) return fits ? CG_SX_BINNED : CG_SX_ATOMIC;
-  if (requested == CG_SX_BINNED && !fits) return -1;
-  return requested;
+  if (o.sx_algo == CG_SX_AUTO) {
+    if (rows_ok && cg::rows_route_pays(n, d, nnz, m, B)) return CG_SX_ROWS;
+    return fits ? CG_SX_BINNED : CG_SX_ATOMIC;
+  }
+  if (o.sx_algo == CG_SX_BINNED && !fits) return kNoBinned;
+  return o.sx_algo;
 }
 
-// Forward workspace: [S X unless sx_out][split partials][S X scratch]
+int algo_fail(int algo, bool csr) {
+  if (algo == kNoRows)
+    return fail(CG_EUNSUPPORTED, "the rows route needs FP32 CSR data, native precision and no sx_out");
+  return fail(CG_EUNSUPPORTED, csr ? "binned S X needs FP32 data and at most %d bucket ranges"
+                                   : "binned S X needs FP32 data, d <= 64 and at most %d bucket ranges",
+              csr ? cg::kBinMaxRangesCsr : cg::kBinMaxRangesDense);
+}
+
+// Forward workspace: [S X unless sx_out or ROWS][split partials][S X scratch]
 struct FwdLayout {
   cg::GsxPlan plan;
   int algo = CG_SX_ATOMIC;
@@ -124,8 +141,14 @@ FwdLayout forward_layout(int dtype, bool csr, int64_t n, int64_t d, int64_t nnz,
                          int64_t B, const Opts& o) {
   FwdLayout L;
   const size_t es = elem_size(dtype);
-  L.algo = resolve_algo(dtype, csr, n, d, B, o.sx_algo);
+  L.algo = resolve_algo(dtype, csr, n, d, nnz, m, B, o);
   L.plan = cg::plan_gsx(m, B, d, to_prec(o.precision), o.kc, es);
+  if (L.algo == CG_SX_ROWS) {
+    L.plan.parts = cg::rows_parts(n, cg::rows_per_wave(n));
+    L.part = 0;
+    L.total = cg::align256((size_t)L.plan.parts * m * d * es);
+    return L;
+  }
   const size_t sx_bytes = o.sx_out ? 0 : cg::align256((size_t)B * d * es);
   const size_t part_bytes = cg::align256((size_t)L.plan.parts * m * d * es);
   size_t scratch_bytes = 0;
@@ -162,6 +185,31 @@ int forward_typed(const int32_t* row_ptr, const int32_t* col_idx, const T* X, in
   hipError_t e;
   int st;
   if ((st = record(o, 0))) return st;
+  if (L.algo == CG_SX_ROWS) {
+    if constexpr (sizeof(T) == 4) {
+      if ((st = record(o, 1))) return st;
+      if ((st = record(o, 2))) return st;
+      cg::GsxArgs a{};
+      a.part = part;
+      a.B = B;
+      a.d = (int32_t)d;
+      a.m = (int32_t)m;
+      a.key = key;
+      a.row_ptr = row_ptr;
+      a.col_idx = col_idx;
+      a.vals = X;
+      a.n = n;
+      a.row_offset = off;
+      a.nnz = (int32_t)nnz;
+      a.route = 1;
+      e = cg::launch_rows_partials(a, o.stream);
+      if (e != hipSuccess) return hip_fail(e, "rows route");
+      if ((st = record(o, 3))) return st;
+      e = cg::launch_splitk_reduce<T>(part, L.plan.parts, m * d, Y, o.stream);
+      if (e != hipSuccess) return hip_fail(e, "split reduction");
+      return record(o, 4);
+    }
+  }
   if (L.algo == CG_SX_BINNED) {
     if constexpr (sizeof(T) == 4) {
       void* scratch = ws + L.scratch;
@@ -243,14 +291,14 @@ int cg_workspace_bytes(int kind, int dtype, int64_t n, int64_t d, int64_t m, int
       if (nnz < 0) return fail(CG_EINVAL, "nnz = %lld < 0", (long long)nnz);
       {
         const FwdLayout L = forward_layout(dtype, true, n, d, nnz, m, B, o);
-        if (L.algo < 0) return fail(CG_EUNSUPPORTED, "binned S X does not apply to these sizes");
+        if (L.algo < 0) return algo_fail(L.algo, true);
         *bytes = L.total;
       }
       return CG_OK;
     case CG_KIND_DENSE:
       {
         const FwdLayout L = forward_layout(dtype, false, n, d, 0, m, B, o);
-        if (L.algo < 0) return fail(CG_EUNSUPPORTED, "binned S X does not apply to these sizes");
+        if (L.algo < 0) return algo_fail(L.algo, false);
         *bytes = L.total;
       }
       return CG_OK;
@@ -277,7 +325,7 @@ int cg_sketch_csr(const int32_t* row_ptr, const int32_t* col_idx, const void* va
   if (o.sx_algo == CG_SX_SORTED && n > 0x7fffffffLL)
     return fail(CG_EUNSUPPORTED, "sorted S X needs n < 2^31");
   const FwdLayout L = forward_layout(dtype, true, n, d, nnz, m, B, o);
-  if (L.algo < 0) return fail(CG_EUNSUPPORTED, "binned S X needs FP32 data and at most %d bucket ranges", cg::kBinMaxRangesCsr);
+  if (L.algo < 0) return algo_fail(L.algo, true);
   if ((st = check_workspace(o, L.total))) return st;
   if (dtype == CG_DTYPE_F64)
     return forward_typed<double>(row_ptr, col_idx, (const double*)vals, 0, true, n, d, nnz, m, B,
@@ -297,7 +345,7 @@ int cg_sketch_dense(const void* X, int64_t ldx, int dtype, int64_t n, int64_t d,
   if (o.sx_algo == CG_SX_SORTED && n > 0x7fffffffLL)
     return fail(CG_EUNSUPPORTED, "sorted S X needs n < 2^31");
   const FwdLayout L = forward_layout(dtype, false, n, d, 0, m, B, o);
-  if (L.algo < 0) return fail(CG_EUNSUPPORTED, "binned S X needs FP32 data, d <= 64 and at most %d bucket ranges", cg::kBinMaxRangesDense);
+  if (L.algo < 0) return algo_fail(L.algo, false);
   if ((st = check_workspace(o, L.total))) return st;
   if (dtype == CG_DTYPE_F64)
     return forward_typed<double>(nullptr, nullptr, (const double*)X, ldx, false, n, d, 0, m, B,

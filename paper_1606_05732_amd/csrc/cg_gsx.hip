@@ -472,6 +472,179 @@ __global__ __launch_bounds__(64 * kRedWaves) void splitk_reduce_kernel(const T* 
   splitk_reduce_block<T>(part, P, md, Y, blockIdx.x);
 }
 
+// ------------------------------------------------------------ rows route
+// Y = sum over the nonempty rows r of X of sigma(r) G[:, h(r)] x_r^T: S
+// sends row r to column h(r) of S X with sign sigma(r), so this is G (S X)
+// taken row by row, and S X is never formed.
+//
+// Wavefront w of workgroup `bx` takes rows [(4 bx + w) R, (4 bx + w + 1) R)
+// with R = a.kc (rows_per_wave), 256 at a time (four per lane).  It
+// compacts the nonempty ones -- packed hash, first entry, end -- into its
+// LDS in row order (ballots and bit counts, no LDS scan).  The window's
+// entries, one contiguous segment of col_idx / vals, are copied into its
+// LDS with independent loads when they fit (kRowsWinEntries), so that the
+// steps below do not each wait for memory.  It then takes the rows four at
+// a time as the K slots of the 16x16x4 MFMAs: lane (p, kq) draws the
+// Philox block of G column h(row kq), row quad p, with the row's sign
+// applied, and the four rows' entries are added into a dense
+// wavefront-private LDS tile, from which the B operand is read.
+// In half groups lanes p >= 8 draw the blocks of the next four rows (as in
+// the S X contraction), so a step covers eight rows.  Every LDS array is
+// private to its wavefront until the closing block reduction.
+constexpr int kRowsWin = 256;          // rows per wavefront window
+constexpr int kRowsWinEntries = 1024;  // a window's entries copied to LDS (at most)
+// per wavefront: hash, start, end (kRowsWin each) | 8 x 64 tile | entries' columns, values
+constexpr int kRowsWaveWords = 3 * kRowsWin + 8 * 64 + 2 * kRowsWinEntries;
+
+template <int NB>
+constexpr int rows_lds_elems() {
+  return red_elems<float, NB>() > kWaves * kRowsWaveWords ? red_elems<float, NB>()
+                                                          : kWaves * kRowsWaveWords;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NB, bool HALF>
+__device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int group, int ng,
+                                              float* lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = lane & 15, kq = lane >> 4;
+  uint32_t* rh = (uint32_t*)lds + wave * kRowsWaveWords;
+  int32_t* rs = (int32_t*)(rh + kRowsWin);
+  int32_t* re = rs + kRowsWin;
+  float* tile = (float*)(re + kRowsWin);
+  int32_t* ecol = (int32_t*)(tile + 8 * 64);
+  float* eval = (float*)(ecol + kRowsWinEntries);
+  constexpr int STEP = HALF ? 8 : 4;   // compacted rows per step
+  const uint32_t q = (uint32_t)(16 * group + (HALF ? (p & 7) : p));
+  const int n0 = ng * NB * 16, d = a.d, m = a.m;
+  const int32_t nnz = a.nnz;
+  const int32_t* __restrict__ row_ptr = a.row_ptr;
+  const int32_t* __restrict__ col_idx = a.col_idx;
+  const float* __restrict__ vals = a.vals;
+  v4f acc[4][NB];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
+  const int64_t w0 = (bx * kWaves + wave) * (int64_t)a.kc;
+  const int64_t w1 = min(w0 + (int64_t)a.kc, a.n);
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int64_t r0 = w0; r0 < w1; r0 += kRowsWin) {
+    // this lane's rows r0 + 4 lane + j: bounds (clamped, non-decreasing)
+    // and packed hashes
+    const int64_t rl = r0 + 4 * lane;
+    int32_t rp[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) rp[j] = min(max(row_ptr[min(rl + j, w1)], 0), nnz);
+#pragma unroll
+    for (int j = 1; j < 5; ++j) rp[j] = max(rp[j], rp[j - 1]);
+    uint32_t hv[4] = {0u, 0u, 0u, 0u};
+    if (rl < w1) hash4(a.row_offset + (uint64_t)rl, (uint32_t)a.B, a.key.k0, a.key.k1, hv);
+    // compaction in row order: the rank of row (lane, j) is the number of
+    // nonempty rows of lower lanes plus this lane's before j
+    uint64_t mk[4];
+    int ne = 0;
+    uint32_t rank = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      mk[j] = __ballot(rp[j + 1] > rp[j]);
+      ne += __popcll(mk[j]);
+      rank += __popcll(mk[j] & lt);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (rp[j + 1] > rp[j]) {
+        rh[rank] = hv[j];
+        rs[rank] = rp[j];
+        re[rank] = rp[j + 1];
+        ++rank;
+      }
+    wave_sync();
+    // the window's entries [es, ee): into LDS when they fit, four
+    // independent loads per lane at a time
+    const int32_t es = ne ? rs[0] : 0, ee = ne ? re[ne - 1] : 0;
+    const int32_t cnt = ee > es ? ee - es : 0;
+    const bool bulk = cnt <= kRowsWinEntries;
+    if (bulk) {
+      for (int32_t i0 = 0; i0 < cnt; i0 += 256) {
+        int32_t cc[4];
+        float vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t k = es + min(i0 + lane + 64 * u, cnt - 1);
+          cc[u] = col_idx[k];
+          vv[u] = vals[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + lane + 64 * u < cnt) {
+            ecol[i0 + lane + 64 * u] = cc[u];
+            eval[i0 + lane + 64 * u] = vv[u];
+          }
+      }
+      wave_sync();
+    }
+    for (int e0 = 0; e0 < ne; e0 += STEP) {
+      const int eN = min(e0 + STEP, ne);
+      // the step's rows laid out dense: tile[i][c - n0] for row e0 + i
+#pragma unroll
+      for (int i = lane; i < STEP * 16; i += 64) ((v4f*)tile)[i] = v4f{0, 0, 0, 0};
+      wave_sync();
+      const int32_t k0 = rs[e0], k1 = re[eN - 1];
+      for (int32_t k = k0 + lane; k < k1; k += 64) {
+        int t = 0;
+#pragma unroll
+        for (int i = 1; i < STEP; ++i) t += (e0 + i < eN && k >= rs[e0 + i]) ? 1 : 0;
+        const int32_t c = bulk ? ecol[k - es] : col_idx[k];
+        const float v = bulk ? eval[k - es] : vals[k];
+        if (c >= n0 && c < n0 + 16 * NB && c < d) atomicAdd(&tile[t * 64 + (c - n0)], v);
+      }
+      wave_sync();
+      // A: the normals of this lane's row (lanes p >= 8 of a half group:
+      // the row four further on), sign applied, zero past the last row
+      const int e = e0 + (HALF ? 4 * (p >> 3) : 0) + kq;
+      const bool ok = e < eN;
+      const uint32_t hp = ok ? rh[e] : 0u;
+      float g[4];
+      box_muller(gauss_block(hash_bucket(hp), q, a.key.k0, a.key.k1), g);
+      const float sg = ok ? (hash_negative(hp) ? -1.0f : 1.0f) : 0.0f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) g[t] *= sg;
+#pragma unroll
+      for (int h = 0; h < (HALF ? 2 : 1); ++h) {
+        float av[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av[t] = !HALF ? g[t] : h ? from_lane_p8(g[t]) : (p < 8 ? g[t] : 0.0f);
+        float xv[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) xv[nb] = tile[(4 * h + kq) * 64 + nb * 16 + p];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(av[t], xv[nb], acc[t][nb]);
+      }
+      wave_sync();   // the tile's reads come before the next step's zeroing
+    }
+  }
+  __syncthreads();   // every wavefront is done with its LDS before the block reduction reuses it
+  block_reduce_store<float, NB, v4f>(acc, lds, wave, lane, group, n0, m, d,
+                                     a.part + (size_t)bx * m * d);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void gx_rows_kernel(GsxArgs a) {
+  __shared__ __align__(16) float lds[rows_lds_elems<NB>()];
+  if (half_group(a.m, (int)blockIdx.y))
+    gx_rows_block<NB, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+  else
+    gx_rows_block<NB, false>(a, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+}
+
 // Batched forms: item -> instance from the item table; the local index is
 // split into (part, row group, column group) with the part fastest.
 __global__ __launch_bounds__(kThreads) void gsx_batched_kernel(const GsxArgs* __restrict__ args,
@@ -484,11 +657,18 @@ __global__ __launch_bounds__(kThreads) void gsx_batched_kernel(const GsxArgs* __
   j /= a.parts;
   const int group = (int)(j % a.mgroups);
   const int ng = (int)(j / a.mgroups);
-  __shared__ float red[red_elems<float, 4>()];
-  if (half_group(a.m, group))
+  __shared__ __align__(16) float red[rows_lds_elems<4>()];
+  const bool half = half_group(a.m, group);
+  if (a.route == 1) {
+    if (half)
+      gx_rows_block<4, true>(a, bx, group, ng, red);
+    else
+      gx_rows_block<4, false>(a, bx, group, ng, red);
+  } else if (half) {
     gsx_native_block<float, 4, true>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
-  else
+  } else {
     gsx_native_block<float, 4, false>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
+  }
 }
 
 __global__ __launch_bounds__(64 * kRedWaves) void splitk_batched_kernel(
@@ -582,6 +762,22 @@ hipError_t launch_gsx_partials(const GsxPlan& pl, Prec prec, const T* SX, int64_
 template <typename T>
 hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, hipStream_t s) {
   splitk_reduce_kernel<T><<<(unsigned)((md + 63) / 64), 64 * kRedWaves, 0, s>>>(part, parts, md, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_partials(const GsxArgs& a0, hipStream_t s) {
+  GsxArgs a = a0;
+  a.kc = rows_per_wave(a.n);
+  const int64_t parts = rows_parts(a.n, a.kc);
+  const int nb = a.d >= 64 ? 4 : (a.d + 15) / 16;
+  const int mgroups = (a.m + 63) / 64, ngroups = (a.d + 16 * nb - 1) / (16 * nb);
+  dim3 grid((unsigned)parts, (unsigned)mgroups, (unsigned)ngroups);
+  switch (nb) {
+    case 1: gx_rows_kernel<1><<<grid, kThreads, 0, s>>>(a); break;
+    case 2: gx_rows_kernel<2><<<grid, kThreads, 0, s>>>(a); break;
+    case 3: gx_rows_kernel<3><<<grid, kThreads, 0, s>>>(a); break;
+    default: gx_rows_kernel<4><<<grid, kThreads, 0, s>>>(a); break;
+  }
   return hipGetLastError();
 }
 

@@ -154,10 +154,49 @@ hipError_t launch_gsx_partials(const GsxPlan& plan, Prec prec, const T* SX, int6
 template <typename T>
 hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, hipStream_t s);
 
+// ---- rows route (no S X) ----------------------------------------------
+// Y = sum over the nonempty rows r of CSR X of sigma(r) G[:, h(r)] x_r^T,
+// the same product as G (S X) taken row by row.  Workgroup p of the split
+// takes 4 rpw consecutive rows (rpw per wavefront: a multiple of 256 from
+// 256 to 2048, about n / 4096 so that a small X still gives some thousand
+// workgroups) and writes one partial m x d product, reduced as the S X
+// route's partials are.
+inline int rows_per_wave(int64_t n) {
+  const int64_t r = (n + 4095) / 4096;
+  const int64_t w = (r + 255) / 256 * 256;
+  return (int)(w < 256 ? 256 : w > 2048 ? 2048 : w);
+}
+inline int64_t rows_parts(int64_t n, int rpw) {
+  const int64_t per = 4 * (int64_t)rpw;
+  return (n + per - 1) / per;
+}
+// A batch has parallelism enough across its instances: there each
+// wavefront takes the most rows, for the fewest partials.
+constexpr int kBatchedRowsPerWave = 2048;
+
+// Whether the rows route costs less than S X plus G (S X).  Work per
+// column of G -- a nonempty row on the rows route, a bucket on the S X
+// route -- is m normals plus one 16x16x4 MFMA per 16 columns of X and 64
+// rows of G (about 13 normals' time each).  The S X route also moves S X
+// twice (write and read: about 3 per element) and every stored entry as an
+// item (about 6 per entry); the rows route adds each entry into an LDS
+// tile (about 4).  The row_ptr reads and hashes, common to both, cancel.
+// Nonempty rows are at most min(n, nnz).
+inline bool rows_route_pays(int64_t n, int64_t d, int64_t nnz, int64_t m, int64_t B) {
+  const double col = (double)m + 13.0 * (double)((d + 15) / 16) * (double)((m + 63) / 64);
+  const double rows = (double)(n < nnz ? n : nnz) * col + 4.0 * (double)nnz;
+  const double sx = (double)B * (col + 3.0 * (double)d) + 6.0 * (double)nnz;
+  return rows < sx;
+}
+
 // Contraction of many instances (FP32, native precision).  Instance i:
 // Y_i = G_i SX_i with its own key, split over B into `parts` chunks of
 // 4 kc columns; its work items are parts x mgroups x ngroups (64 rows of G
-// by 64 columns of S X each), then ceil(m d / 64) reduction items.
+// by 64 columns of S X each), then ceil(m d / 64) reduction items.  An
+// instance on the rows route (route = 1) has no S X: its parts split the
+// rows instead (rows_parts(n, kc) of them, kc = kBatchedRowsPerWave rows
+// per wavefront), from row_ptr / col_idx / vals.  The single-instance rows
+// route takes the same arguments.
 struct GsxArgs {
   const float* SX;
   float* part;   // parts x m x d
@@ -165,7 +204,19 @@ struct GsxArgs {
   int64_t B;
   int32_t d, m, kc, parts, mgroups, ngroups;
   Key key;
+  // rows route
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const float* vals;
+  int64_t n;
+  uint64_t row_offset;
+  int32_t nnz, route;
 };
+
+// Partial products of the rows route, one per workgroup of the split
+// (grid rows_parts(n, rows_per_wave(n)) x mgroups x ngroups; a.part
+// receives them; a.kc is ignored).
+hipError_t launch_rows_partials(const GsxArgs& a, hipStream_t s);
 hipError_t launch_gsx_batched(const GsxArgs* args, const int32_t* gsx_inst,
                               const int32_t* gsx_first, int64_t items, hipStream_t s);
 hipError_t launch_splitk_batched(const GsxArgs* args, const int32_t* red_inst,

@@ -38,6 +38,15 @@ def _ceil(a, b):
     return -(-a // b)
 
 
+def _rows_route(n, d, nnz, m, B):
+    """The planner's route rule, restated: work per column of G (a nonempty
+    row, or a bucket) is m normals plus 13 per 16x16x4 MFMA (one per 16
+    columns of X and 64 rows of G); the S X route adds 3 per S X element and
+    6 per entry, the rows route 4 per entry; nonempty rows <= min(n, nnz)."""
+    col = m + 13.0 * _ceil(d, 16) * _ceil(m, 64)
+    return min(n, nnz) * col + 4.0 * nnz < B * (col + 3.0 * d) + 6.0 * nnz
+
+
 def test_plan_fields_follow_the_shapes():
     shapes = [(1, 1, 0, 1, 1), (100000, 8, 5000, 32, 2048), (40000, 64, 90000, 70, 10000),
               (16384, 32, 26000, 32, 32768), (16385, 16, 1, 5, 7)]
@@ -46,15 +55,24 @@ def test_plan_fields_follow_the_shapes():
     assert st == L.CG_OK, L.last_error()
     first = {"tile": 0, "range": 0, "gsx": 0, "red": 0}
     prev_off = 0
+    routes = [_rows_route(*sh) for sh in shapes]
+    assert routes == [True, False, False, True, True]   # both routes are covered
     for i, (n, d, nnz, m, B) in enumerate(shapes):
         c = t[i]
-        # tuning defaults: 16384 rows per tile, kc 512
-        assert c.tile_rows == 16384
-        assert c.tiles == _ceil(n, 16384)
-        # ranges of 2^bp_shift buckets, 2^bp_shift * d <= 8192 (64 KB of int64 cells)
-        assert (1 << c.bp_shift) * d <= 8192 < (2 << c.bp_shift) * d or c.bp_shift == 30
-        assert c.ranges == _ceil(B, 1 << c.bp_shift)
-        assert c.kc == 512 and c.parts == _ceil(B, 4 * 512)
+        assert c.route == int(routes[i])
+        if routes[i]:
+            # rows route: no S X work; parts of 4 kc rows, kc = 2048 rows per
+            # wavefront in a batch
+            assert (c.tile_rows, c.tiles, c.ranges, c.bp_shift) == (0, 0, 0, 0)
+            assert c.kc == 2048 and c.parts == _ceil(n, 4 * 2048)
+        else:
+            # tuning defaults: 16384 rows per tile, kc 512
+            assert c.tile_rows == 16384
+            assert c.tiles == _ceil(n, 16384)
+            # ranges of 2^bp_shift buckets, 2^bp_shift * d <= 8192 (64 KB of int64 cells)
+            assert (1 << c.bp_shift) * d <= 8192 < (2 << c.bp_shift) * d or c.bp_shift == 30
+            assert c.ranges == _ceil(B, 1 << c.bp_shift)
+            assert c.kc == 512 and c.parts == _ceil(B, 4 * 512)
         assert c.gsx_items == c.parts * _ceil(m, 64) * _ceil(d, 64)
         assert c.red_items == _ceil(m * d, 64)
         assert (c.first_tile, c.first_range, c.first_gsx, c.first_red) == \
@@ -65,9 +83,24 @@ def test_plan_fields_follow_the_shapes():
         first["red"] += c.red_items
         assert c.ws_off % 256 == 0 and c.ws_off > prev_off
         prev_off = c.ws_off
-    # the last instance's scratch (items, S X, partials) fits in the workspace
+    # the last instance's scratch (rows route: its partials) fits in the workspace
     n, d, nnz, m, B = shapes[-1]
-    assert ws >= t[-1].ws_off + 8 * nnz + 4 * B * d + 4 * t[-1].parts * m * d
+    assert ws >= t[-1].ws_off + 4 * t[-1].parts * m * d
+    # and an S X instance's (items, S X, partials)
+    n, d, nnz, m, B = shapes[2]
+    assert t[3].ws_off >= t[2].ws_off + 8 * nnz + 4 * B * d + 4 * t[2].parts * m * d
+
+
+@pytest.mark.parametrize("n,d,nnz,m,B", [
+    (16777216, 32, 26847020, 64, 65536), (500000, 64, 64000, 32, 125000), (100000, 16, 800000, 32, 8192),
+    (100000, 16, 8000, 32, 8192), (1000000, 8, 16000, 32, 2048), (1000000, 8, 400000, 32, 2048),
+    (3000, 130, 9000, 100, 50000), (5, 3, 2, 70, 3),
+])
+def test_route_follows_the_cost_rule(n, d, nnz, m, B):
+    t = _table([(n, d, nnz, m, B)])
+    st, _ = _plan(t)
+    assert st == L.CG_OK, L.last_error()
+    assert t[0].route == int(_rows_route(n, d, nnz, m, B))
 
 
 def test_tuning_table_drives_the_plan():
@@ -75,10 +108,10 @@ def test_tuning_table_drives_the_plan():
     rows = (ctypes.c_int32 * 11)(*([4096] * 11))
     kc = (ctypes.c_int32 * 11)(*([128] * 11))
     assert lib.cg_set_tuning(rows, kc, 11) == L.CG_OK
-    t = _table([(100000, 16, 8000, 32, 8192)])
+    t = _table([(100000, 16, 800000, 32, 8192)])   # S X route
     st, _ = _plan(t)
     assert st == L.CG_OK
-    assert t[0].tile_rows == 4096 and t[0].tiles == _ceil(100000, 4096)
+    assert t[0].route == 0 and t[0].tile_rows == 4096 and t[0].tiles == _ceil(100000, 4096)
     assert t[0].kc == 128 and t[0].parts == _ceil(8192, 512)
     got_r, got_k = (ctypes.c_int32 * 11)(), (ctypes.c_int32 * 11)()
     assert lib.cg_get_tuning(got_r, got_k, 11) == L.CG_OK
