@@ -600,8 +600,11 @@ __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int 
         int t = 0;
 #pragma unroll
         for (int i = 1; i < STEP; ++i) t += (e0 + i < eN && k >= rs[e0 + i]) ? 1 : 0;
-        const int32_t c = bulk ? ecol[k - es] : col_idx[k];
-        const float v = bulk ? eval[k - es] : vals[k];
+        // (k - es is inside the copied segment for well-formed row_ptr;
+        // clamped all the same, like every index taken from row_ptr)
+        const int32_t kl = min(max(k - es, 0), kRowsWinEntries - 1);
+        const int32_t c = bulk ? ecol[kl] : col_idx[k];
+        const float v = bulk ? eval[kl] : vals[k];
         if (c >= n0 && c < n0 + 16 * NB && c < d) atomicAdd(&tile[t * 64 + (c - n0)], v);
       }
       wave_sync();
