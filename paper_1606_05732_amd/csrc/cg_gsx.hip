@@ -493,8 +493,9 @@ __global__ __launch_bounds__(64 * kRedWaves) void splitk_reduce_kernel(const T* 
 // private to its wavefront until the closing block reduction.
 constexpr int kRowsWin = 256;          // rows per wavefront window
 constexpr int kRowsWinEntries = 1024;  // a window's entries copied to LDS (at most)
-// per wavefront: hash, start, end (kRowsWin each) | 8 x 64 tile | entries' columns, values
-constexpr int kRowsWaveWords = 3 * kRowsWin + 8 * 64 + 2 * kRowsWinEntries;
+constexpr int kRowsPhase = 16;         // rows whose tile is built at once
+// per wavefront: hash, start, end (kRowsWin each) | kRowsPhase x 64 tile | entries' columns, values
+constexpr int kRowsWaveWords = 3 * kRowsWin + kRowsPhase * 64 + 2 * kRowsWinEntries;
 
 template <int NB>
 constexpr int rows_lds_elems() {
@@ -517,9 +518,9 @@ __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int 
   int32_t* rs = (int32_t*)(rh + kRowsWin);
   int32_t* re = rs + kRowsWin;
   float* tile = (float*)(re + kRowsWin);
-  int32_t* ecol = (int32_t*)(tile + 8 * 64);
+  int32_t* ecol = (int32_t*)(tile + kRowsPhase * 64);
   float* eval = (float*)(ecol + kRowsWinEntries);
-  constexpr int STEP = HALF ? 8 : 4;   // compacted rows per step
+  constexpr int STEP = HALF ? 8 : 4;   // compacted rows per MFMA step
   const uint32_t q = (uint32_t)(16 * group + (HALF ? (p & 7) : p));
   const int n0 = ng * NB * 16, d = a.d, m = a.m;
   const int32_t nnz = a.nnz;
@@ -589,17 +590,23 @@ __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int 
       }
       wave_sync();
     }
-    for (int e0 = 0; e0 < ne; e0 += STEP) {
-      const int eN = min(e0 + STEP, ne);
-      // the step's rows laid out dense: tile[i][c - n0] for row e0 + i
+    for (int e0 = 0; e0 < ne; e0 += kRowsPhase) {
+      const int eN = min(e0 + kRowsPhase, ne);
+      // the phase's rows laid out dense: tile[i][c - n0] for row e0 + i
 #pragma unroll
-      for (int i = lane; i < STEP * 16; i += 64) ((v4f*)tile)[i] = v4f{0, 0, 0, 0};
+      for (int i = lane; i < kRowsPhase * 16; i += 64) ((v4f*)tile)[i] = v4f{0, 0, 0, 0};
+      // the starts of rows e0 + 1 .. e0 + kRowsPhase - 1 as wavefront-uniform
+      // values (rows past eN never match)
+      const int32_t my_start = lane < kRowsPhase && e0 + lane < eN ? rs[e0 + lane] : INT32_MAX;
+      int32_t st[kRowsPhase];
+#pragma unroll
+      for (int i = 1; i < kRowsPhase; ++i) st[i] = __builtin_amdgcn_readlane(my_start, i);
       wave_sync();
       const int32_t k0 = rs[e0], k1 = re[eN - 1];
       for (int32_t k = k0 + lane; k < k1; k += 64) {
         int t = 0;
 #pragma unroll
-        for (int i = 1; i < STEP; ++i) t += (e0 + i < eN && k >= rs[e0 + i]) ? 1 : 0;
+        for (int i = 1; i < kRowsPhase; ++i) t += k >= st[i] ? 1 : 0;
         // (k - es is inside the copied segment for well-formed row_ptr;
         // clamped all the same, like every index taken from row_ptr)
         const int32_t kl = min(max(k - es, 0), kRowsWinEntries - 1);
@@ -608,30 +615,36 @@ __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int 
         if (c >= n0 && c < n0 + 16 * NB && c < d) atomicAdd(&tile[t * 64 + (c - n0)], v);
       }
       wave_sync();
-      // A: the normals of this lane's row (lanes p >= 8 of a half group:
-      // the row four further on), sign applied, zero past the last row
-      const int e = e0 + (HALF ? 4 * (p >> 3) : 0) + kq;
-      const bool ok = e < eN;
-      const uint32_t hp = ok ? rh[e] : 0u;
-      float g[4];
-      box_muller(gauss_block(hash_bucket(hp), q, a.key.k0, a.key.k1), g);
-      const float sg = ok ? (hash_negative(hp) ? -1.0f : 1.0f) : 0.0f;
+      // the phase's MFMA steps, STEP rows each, with no LDS fence between them
 #pragma unroll
-      for (int t = 0; t < 4; ++t) g[t] *= sg;
+      for (int s0 = 0; s0 < kRowsPhase; s0 += STEP) {
+        if (e0 + s0 >= eN) break;
+        // A: the normals of this lane's row (lanes p >= 8 of a half group:
+        // the row four further on), sign applied, zero past the last row
+        const int e = e0 + s0 + (HALF ? 4 * (p >> 3) : 0) + kq;
+        const bool ok = e < eN;
+        const uint32_t hp = ok ? rh[e] : 0u;
+        float g[4];
+        box_muller(gauss_block(hash_bucket(hp), q, a.key.k0, a.key.k1), g);
+        const float sg = ok ? (hash_negative(hp) ? -1.0f : 1.0f) : 0.0f;
 #pragma unroll
-      for (int h = 0; h < (HALF ? 2 : 1); ++h) {
-        float av[4];
+        for (int t = 0; t < 4; ++t) g[t] *= sg;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) av[t] = !HALF ? g[t] : h ? from_lane_p8(g[t]) : (p < 8 ? g[t] : 0.0f);
-        float xv[NB];
+        for (int h = 0; h < (HALF ? 2 : 1); ++h) {
+          float av[4];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) xv[nb] = tile[(4 * h + kq) * 64 + nb * 16 + p];
+          for (int t = 0; t < 4; ++t)
+            av[t] = !HALF ? g[t] : h ? from_lane_p8(g[t]) : (p < 8 ? g[t] : 0.0f);
+          float xv[NB];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+          for (int nb = 0; nb < NB; ++nb) xv[nb] = tile[(s0 + 4 * h + kq) * 64 + nb * 16 + p];
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(av[t], xv[nb], acc[t][nb]);
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(av[t], xv[nb], acc[t][nb]);
+        }
       }
-      wave_sync();   // the tile's reads come before the next step's zeroing
+      wave_sync();   // the tile's reads come before the next phase's zeroing
     }
   }
   __syncthreads();   // every wavefront is done with its LDS before the block reduction reuses it
