@@ -236,7 +236,10 @@ typedef struct cg_instance {
   int32_t parts;            /* contraction splits along B (4 kc columns)    */
   int32_t gsx_items;        /* contraction work items                       */
   int32_t red_items;        /* split-reduction work items                   */
-  int32_t first_tile;       /* its first item in each phase's queue         */
+  int32_t first_tile;       /* its first item in each phase's queue (the
+                               contraction queue holds the instances of each
+                               MFMA width, ceil(d/16) up to 4 blocks of 16
+                               columns, together, in increasing width)    */
   int32_t first_range;
   int32_t first_gsx;
   int32_t first_red;

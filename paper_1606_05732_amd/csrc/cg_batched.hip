@@ -98,6 +98,7 @@ size_t instance_bytes(int64_t R, int64_t tiles, int64_t nnz, int64_t B, int64_t 
 struct Plan {
   std::vector<cg_instance> inst;
   int64_t tiles = 0, ranges = 0, gsx = 0, red = 0;
+  int64_t gsx_by_nb[4] = {0, 0, 0, 0};   // contraction items of each width
   int r_max = 1;
   size_t reduce_lds = 0;
   Header header;
@@ -157,8 +158,9 @@ int make_plan(const cg_instance* src, int32_t count, Plan* p) {
     c.red_items = (int32_t)red;
     c.first_tile = (int32_t)p->tiles;
     c.first_range = (int32_t)p->ranges;
-    c.first_gsx = (int32_t)p->gsx;
+    c.first_gsx = (int32_t)p->gsx_by_nb[batched_nb(c.d) - 1];   // within its width; based below
     c.first_red = (int32_t)p->red;
+    p->gsx_by_nb[batched_nb(c.d) - 1] += c.gsx_items;
     p->tiles += c.tiles;
     p->ranges += c.ranges;
     p->gsx += c.gsx_items;
@@ -171,6 +173,11 @@ int make_plan(const cg_instance* src, int32_t count, Plan* p) {
     sizes[i] = rows ? align256((size_t)(parts * c.m * c.d * 4))
                     : instance_bytes(g.R, g.ntiles, c.nnz, c.B, c.d, parts, c.m);
   }
+  // the contraction queue: the items of each width together, in increasing width
+  int64_t base[4] = {0, 0, 0, 0};
+  for (int k = 1; k < 4; ++k) base[k] = base[k - 1] + p->gsx_by_nb[k - 1];
+  for (int32_t i = 0; i < count; ++i)
+    p->inst[i].first_gsx += (int32_t)base[batched_nb(p->inst[i].d) - 1];
   p->header = header_layout(count, p->tiles, p->ranges, p->gsx, p->red);
   size_t off = p->header.bytes;
   for (int32_t i = 0; i < count; ++i) {
@@ -307,7 +314,7 @@ int cg_sketch_batched(const cg_instance* inst, int32_t count, const cg_opts* opt
   e = cg::launch_sx_binned_batched(bargs, tile_inst, firsts, p.tiles, range_inst, firsts + count,
                                    p.ranges, p.r_max, p.reduce_lds, s);
   if (e != hipSuccess) return cg::failf(CG_EHIP, "batched S X: %s", hipGetErrorString(e));
-  e = cg::launch_gsx_batched(gargs, gsx_inst, firsts + 2 * count, p.gsx, s);
+  e = cg::launch_gsx_batched(gargs, gsx_inst, firsts + 2 * count, p.gsx_by_nb, s);
   if (e != hipSuccess) return cg::failf(CG_EHIP, "batched contraction: %s", hipGetErrorString(e));
   e = cg::launch_splitk_batched(gargs, red_inst, firsts + 3 * count, p.red, s);
   if (e != hipSuccess) return cg::failf(CG_EHIP, "batched reduction: %s", hipGetErrorString(e));

@@ -662,28 +662,34 @@ __global__ __launch_bounds__(kThreads) void gx_rows_kernel(GsxArgs a) {
 }
 
 // Batched forms: item -> instance from the item table; the local index is
-// split into (part, row group, column group) with the part fastest.
+// split into (part, row group, column group) with the part fastest.  One
+// kernel per width NB (16-column blocks per wavefront), launched over the
+// items of the instances of that width: `base` is the first of them in the
+// queue.
+template <int NB>
 __global__ __launch_bounds__(kThreads) void gsx_batched_kernel(const GsxArgs* __restrict__ args,
                                                                const int32_t* __restrict__ inst,
-                                                               const int32_t* __restrict__ first) {
-  const int i = inst[blockIdx.x];
+                                                               const int32_t* __restrict__ first,
+                                                               int64_t base) {
+  const int64_t item = base + blockIdx.x;
+  const int i = inst[item];
   const GsxArgs a = args[i];
-  int64_t j = (int64_t)blockIdx.x - first[i];
+  int64_t j = item - first[i];
   const int64_t bx = j % a.parts;
   j /= a.parts;
   const int group = (int)(j % a.mgroups);
   const int ng = (int)(j / a.mgroups);
-  __shared__ __align__(16) float red[rows_lds_elems<4>()];
+  __shared__ __align__(16) float red[rows_lds_elems<NB>()];
   const bool half = half_group(a.m, group);
   if (a.route == 1) {
     if (half)
-      gx_rows_block<4, true>(a, bx, group, ng, red);
+      gx_rows_block<NB, true>(a, bx, group, ng, red);
     else
-      gx_rows_block<4, false>(a, bx, group, ng, red);
+      gx_rows_block<NB, false>(a, bx, group, ng, red);
   } else if (half) {
-    gsx_native_block<float, 4, true>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
+    gsx_native_block<float, NB, true>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
   } else {
-    gsx_native_block<float, 4, false>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
+    gsx_native_block<float, NB, false>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
   }
 }
 
@@ -798,9 +804,24 @@ hipError_t launch_rows_partials(const GsxArgs& a0, hipStream_t s) {
 }
 
 hipError_t launch_gsx_batched(const GsxArgs* args, const int32_t* gsx_inst,
-                              const int32_t* gsx_first, int64_t items, hipStream_t s) {
-  if (items > 0) gsx_batched_kernel<<<(unsigned)items, kThreads, 0, s>>>(args, gsx_inst, gsx_first);
-  return hipGetLastError();
+                              const int32_t* gsx_first, const int64_t items_by_nb[4],
+                              hipStream_t s) {
+  int64_t base = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t n = items_by_nb[k];
+    if (n > 0) {
+      switch (k) {
+        case 0: gsx_batched_kernel<1><<<(unsigned)n, kThreads, 0, s>>>(args, gsx_inst, gsx_first, base); break;
+        case 1: gsx_batched_kernel<2><<<(unsigned)n, kThreads, 0, s>>>(args, gsx_inst, gsx_first, base); break;
+        case 2: gsx_batched_kernel<3><<<(unsigned)n, kThreads, 0, s>>>(args, gsx_inst, gsx_first, base); break;
+        default: gsx_batched_kernel<4><<<(unsigned)n, kThreads, 0, s>>>(args, gsx_inst, gsx_first, base); break;
+      }
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    base += n;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_splitk_batched(const GsxArgs* args, const int32_t* red_inst,

@@ -217,8 +217,15 @@ struct GsxArgs {
 // (grid rows_parts(n, rows_per_wave(n)) x mgroups x ngroups; a.part
 // receives them; a.kc is ignored).
 hipError_t launch_rows_partials(const GsxArgs& a, hipStream_t s);
+// 16-column blocks per contraction wavefront of a batched instance: as few
+// as its d needs (one column group below d = 64), else four.  The batch's
+// contraction queue holds the items of each width together, in increasing
+// width; items_by_nb[k] counts those of width k + 1, and each width is its
+// own launch.
+inline int batched_nb(int64_t d) { return d < 64 ? (int)((d + 15) / 16) : 4; }
 hipError_t launch_gsx_batched(const GsxArgs* args, const int32_t* gsx_inst,
-                              const int32_t* gsx_first, int64_t items, hipStream_t s);
+                              const int32_t* gsx_first, const int64_t items_by_nb[4],
+                              hipStream_t s);
 hipError_t launch_splitk_batched(const GsxArgs* args, const int32_t* red_inst,
                                  const int32_t* red_first, int64_t items, hipStream_t s);
 

@@ -75,14 +75,21 @@ def test_plan_fields_follow_the_shapes():
             assert c.kc == 512 and c.parts == _ceil(B, 4 * 512)
         assert c.gsx_items == c.parts * _ceil(m, 64) * _ceil(d, 64)
         assert c.red_items == _ceil(m * d, 64)
-        assert (c.first_tile, c.first_range, c.first_gsx, c.first_red) == \
-            (first["tile"], first["range"], first["gsx"], first["red"])
+        assert (c.first_tile, c.first_range, c.first_red) == \
+            (first["tile"], first["range"], first["red"])
         first["tile"] += c.tiles
         first["range"] += c.ranges
-        first["gsx"] += c.gsx_items
         first["red"] += c.red_items
         assert c.ws_off % 256 == 0 and c.ws_off > prev_off
         prev_off = c.ws_off
+    # the contraction queue holds the items of each MFMA width (16-column
+    # blocks: ceil(d / 16) below d = 64, else 4) together, in increasing width
+    width = lambda d: _ceil(d, 16) if d < 64 else 4
+    order = sorted(range(len(shapes)), key=lambda i: (width(shapes[i][1]), i))
+    q = 0
+    for i in order:
+        assert t[i].first_gsx == q
+        q += t[i].gsx_items
     # the last instance's scratch (rows route: its partials) fits in the workspace
     n, d, nnz, m, B = shapes[-1]
     assert ws >= t[-1].ws_off + 4 * t[-1].parts * m * d
