@@ -239,9 +239,12 @@ def batched(log_fn):
     log_fn(f"batched: sequential {seq_ms:.2f} ms, batch {default_ms:.2f} ms (built-in table), "
            f"{tuned_ms:.2f} ms (autotuned in {res['seconds']:.1f} s)")
     cls = res["classes"]
+    plan = cg.BatchedSketch(items)
+    rows_route = sum(plan.plan_fields(i)["route"] for i in range(len(items)))
+    del plan
     return {"workload": "512 CSR instances, n log-uniform [1e4, 1e6], d in {8,16,32,64}, "
                         "density log-uniform [0.1%, 10%], m = 32, B = min(32 d^2, n/4)",
-            "instances": len(items), "nnz": nnz,
+            "instances": len(items), "nnz": nnz, "rows_route_instances": rows_route,
             "sequential_ms": round(seq_ms, 3), "batched_builtin_ms": round(default_ms, 3),
             "batched_tuned_ms": round(tuned_ms, 3),
             "speedup_vs_sequential": round(seq_ms / tuned_ms, 2),
