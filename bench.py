@@ -15,7 +15,8 @@ Prints ONE JSON line on stdout (everything else goes to stderr):
                against the 8 TB/s HBM peak; `traffic` is the stage's HBM
                bytes per launch from committed rocprofv3 FETCH_SIZE /
                WRITE_SIZE counters scaled by a plain-copy calibration, or
-               null if the kernel sources changed since they were taken
+               null if the kernel sources changed since they were taken, and
+               `traffic_gbs` those bytes over the stage's time
   cpu_baseline the FP64 oracle on the host cores, same workload
   ladder       the G.(S X) precision ladder on the dense spiky workload
                (n = 2^22, d = 64, m = 64, B = 262144): time per step and
@@ -312,6 +313,7 @@ def main():
     # its two ends only) against its algorithmic bytes
     sx_s = sx_stage * 1e-3
     achieved = sx_bytes / sx_s / 1e9
+    traffic = counters_traffic(sx_bytes)
     gsx_flops = 2.0 * w.m * w.B * c.d
     log(f"wall {wall:.4f} ms/step; S X stage {sx_stage*1e3:.1f} us; "
         f"with all stage events: sx prologue {stage['sx_prologue']*1e3:.1f} us, "
@@ -337,7 +339,10 @@ def main():
                      "kernel": f"S.X stage ({args.algo}: bin_count, bin_scan, bin_scatter, bin_reduce)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counters_traffic(sx_bytes),
+                     "traffic": traffic,
+                     # the counted bytes over the same time: how close the stage
+                     # runs to the memory system, whatever it has to move
+                     "traffic_gbs": round(traffic / sx_s / 1e9, 1) if traffic else None,
                      "algorithmic_bytes_per_launch": sx_bytes,
                      "avg_launch_us": round(sx_s * 1e6, 2)},
         # per-stage breakdown from a pass with an event at every stage
