@@ -23,6 +23,8 @@ Prints ONE JSON line on stdout (everything else goes to stderr):
                error against the FP64 oracle for FP32, BF16 and FP8 inputs
   batched      512 uneven CSR instances: 512 sequential calls against one
                batch (built-in tuning table, then autotuned)
+  adjoint      dX = T^T dY at the gradient workload's shape (n = 2^22,
+               d = 64, m = 128, B = 2^19): time per call and its roofline
 """
 import argparse
 import ctypes
@@ -255,6 +257,40 @@ def batched(log_fn):
             "autotune_trials": len(res["trials"]), "autotune_seconds": round(res["seconds"], 2)}
 
 
+def adjoint(steps, warmup):
+    """The adjoint dX = T^T dY = S^T (G^T dY) at the gradient workload's
+    shape (dense dX: n = 2^22, d = 64; m = 128, B = 2^19): Z = G^T dY on
+    MFMA (B x d, G generated in registers), then the signed row gather
+    dX[r] = sigma(r) Z[h(r)].  Timed with events on the launch stream; the
+    roofline counts the bytes the gather must move (dX written, Z read)."""
+    import numpy as np
+    import torch
+
+    import paper_1606_05732_amd as cg
+    n, d, m, B, seed = 1 << 22, 64, 128, 1 << 19, 2004
+    dY = torch.from_numpy(np.random.default_rng(1004).standard_normal((m, d)).astype(np.float32)).cuda()
+    dX = torch.empty((n, d), dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        cg.sketch_adjoint(dY, n, m, B, seed, out=dX)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        cg.sketch_adjoint(dY, n, m, B, seed, out=dX)
+    stop.record()
+    stop.synchronize()
+    t = start.elapsed_time(stop) / steps * 1e-3
+    nbytes = 4 * n * d + 4 * B * d
+    achieved = nbytes / t / 1e9
+    log(f"adjoint: {t * 1e3:.3f} ms per call")
+    return {"workload": f"dense_grad_n{n}_d{d}_m{m}_B{B}", "ms_per_call": round(t * 1e3, 4),
+            "flops_gt_dy": 2.0 * m * B * d, "normals": m * B,
+            "roofline": {"bound": "hbm", "kernel": "adjoint (G^T dY, then the dX gather)",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes_per_launch": nbytes}}
+
+
 def copy_calibration(mib=512, reps=3):
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters: run it under the same rocprofv3 --pmc pass as the
@@ -280,6 +316,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -360,6 +397,8 @@ def main():
         result["ladder"] = ladder(max(5, args.steps // 2), 2, ev)
     if not args.no_batched:
         result["batched"] = batched(log)
+    if not args.no_adjoint:
+        result["adjoint"] = adjoint(max(5, args.steps // 2), 2)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w)
