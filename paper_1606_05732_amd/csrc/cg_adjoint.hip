@@ -50,7 +50,9 @@ __device__ __forceinline__ int d_row(int kq, int r) {
 // One wavefront computes Z for 16 consecutive buckets b and up to 16 NB
 // columns.  MFMA roles: M = bucket (lane % 16), K = row i of G, N = column
 // of dY.  K slot kq of step s holds G row 4 (4 s + kq) + t for sub-step t,
-// so one Philox block (b, 4 s + kq) feeds the four sub-steps.
+// so one Philox block (b, 4 s + kq) feeds the four sub-steps.  (dY is read
+// from memory -- it stays in the caches; staging it in LDS per workgroup
+// cost more occupancy than it saved.)
 template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void gt_dy_kernel(const T* __restrict__ dY, int m, int d,
                                                          int64_t B, Key key, T* __restrict__ Z) {
@@ -126,6 +128,53 @@ __global__ __launch_bounds__(kThreads) void gather_dense_kernel(const T* __restr
     for (int c = c0; c < d; c += lpr) {
       const T v = src[c];
       dst[c] = neg ? -v : v;
+    }
+  }
+}
+
+// FP32 rows whose d is a multiple of 4, with Z, dX and the row stride
+// 16-byte aligned: 16-byte loads and stores, d / 4 lanes per row (rounded
+// up to a power of two, at most 64), and four groups of rows per step, so
+// that every lane has four row reads in flight before its first store.
+// The dX rows are whole lines written once: non-temporal stores, so that Z
+// (read at random rows) keeps the caches.
+__global__ __launch_bounds__(kThreads) void gather_dense_vec_kernel(const float* __restrict__ Z,
+                                                                    int64_t n, int d, uint32_t B,
+                                                                    Key key, uint64_t row_offset,
+                                                                    float* __restrict__ dX,
+                                                                    int64_t lddx) {
+  __shared__ uint32_t s_hash[kWaves][kRowsPerWave];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r0 = ((int64_t)blockIdx.x * kWaves + wave) * kRowsPerWave;
+  const int nr = r0 < n ? (int)min((int64_t)kRowsPerWave, n - r0) : 0;
+  uint32_t* sh = s_hash[wave];
+  if (nr > 0) hash_rows_to_lds(sh, row_offset + (uint64_t)r0, nr, B, key, lane);
+  __syncthreads();
+  if (nr == 0) return;
+  const int d4 = d >> 2;
+  int lpr = 1;
+  while (lpr < d4 && lpr < 64) lpr <<= 1;
+  const int rpp = 64 / lpr;   // rows per wavefront instruction
+  const int sub = lane / lpr, c0 = lane % lpr;
+  constexpr int U = 4;
+  for (int j0 = 0; j0 < nr; j0 += U * rpp) {
+    for (int c = c0; c < d4; c += lpr) {
+      v4f v[U];
+      uint32_t hp[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = min(j0 + u * rpp + sub, nr - 1);   // clamped: a row past nr is reread, not written
+        hp[u] = sh[j];
+        v[u] = ((const v4f*)(Z + (size_t)hash_bucket(hp[u]) * d))[c];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * rpp + sub;
+        if (j < nr) {
+          const v4f w = hash_negative(hp[u]) ? -v[u] : v[u];
+          __builtin_nontemporal_store(w, (v4f*)(dX + (r0 + j) * lddx) + c);
+        }
+      }
     }
   }
 }
@@ -228,6 +277,13 @@ hipError_t launch_gt_dy(const T* dY, int m, int d, int64_t B, Key key, T* Z, hip
 template <typename T>
 hipError_t launch_gather_dense(const T* Z, int64_t n, int d, uint32_t B, Key key,
                                uint64_t row_offset, T* dX, int64_t lddx, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (d % 4 == 0 && lddx % 4 == 0 && ((uintptr_t)Z & 15) == 0 && ((uintptr_t)dX & 15) == 0) {
+      gather_dense_vec_kernel<<<blocks_for_rows(n), kThreads, 0, s>>>(Z, n, d, B, key, row_offset,
+                                                                        dX, lddx);
+      return hipGetLastError();
+    }
+  }
   gather_dense_kernel<T><<<blocks_for_rows(n), kThreads, 0, s>>>(Z, n, d, B, key, row_offset, dX,
                                                                  lddx);
   return hipGetLastError();

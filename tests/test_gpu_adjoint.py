@@ -17,8 +17,11 @@ NPD = {torch.float32: np.float32, torch.float64: np.float64}
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+# d multiple of 4 takes the 16-byte gather (8, 12, 64, 132: two to 33
+# lanes per row), the others the scalar one
 @pytest.mark.parametrize("n,d,m,B", [(1, 1, 1, 1), (3000, 10, 20, 2000), (5003, 64, 128, 4096),
-                                     (999, 17, 70, 333), (500, 130, 9, 100)])
+                                     (999, 17, 70, 333), (500, 130, 9, 100), (7001, 8, 16, 1000),
+                                     (3001, 12, 40, 777), (600, 132, 24, 300)])
 def test_dense_adjoint_parity(cuda, dtype, n, d, m, B):
     rng = np.random.default_rng(n + m)
     dY = rng.standard_normal((m, d)).astype(NPD[dtype])
@@ -28,6 +31,25 @@ def test_dense_adjoint_parity(cuda, dtype, n, d, m, B):
     torch.cuda.synchronize()
     ref = O.adjoint_dense(dY.astype(np.float64), n, d, m, B, seed)
     assert rel(dX.cpu().numpy(), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("pad,shift", [(4, 0), (3, 1)])
+def test_dense_adjoint_into_strided_output(cuda, pad, shift):
+    """dX written into a wider buffer: row stride d + pad, starting `shift`
+    floats in (16-byte aligned rows take the vector gather, the rest the
+    scalar one); the columns around it stay untouched."""
+    n, d, m, B, seed = 4099, 64, 32, 2048, 17
+    rng = np.random.default_rng(5)
+    dY = rng.standard_normal((m, d)).astype(np.float32)
+    buf = torch.full((n, d + pad), 7.0, device=cuda)
+    out = buf[:, shift:shift + d]
+    say("adjoint strided out", pad, shift)
+    cg.sketch_adjoint(torch.from_numpy(dY).to(cuda), n, m, B, seed, out=out)
+    torch.cuda.synchronize()
+    ref = O.adjoint_dense(dY.astype(np.float64), n, d, m, B, seed)
+    assert rel(out.cpu().numpy(), ref) < TOL[torch.float32]
+    rest = torch.cat([buf[:, :shift], buf[:, shift + d:]], dim=1)
+    assert torch.all(rest == 7.0)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
