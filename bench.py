@@ -291,6 +291,40 @@ def adjoint(steps, warmup):
                          "algorithmic_bytes_per_launch": nbytes}}
 
 
+def algos(steps, warmup, ev, X2, w2):
+    """Every S X algorithm on the FP32 CSR workload (X2, already on the GPU),
+    and the FP64 CSR workload (n = 10^6, d = 10, 1% density, m = 20,
+    B = 2000) with its automatic choice (atomic: FP64) and the sorted
+    path: ms per step and the S X stage's time against its algorithmic
+    bytes."""
+    import torch
+
+    import paper_1606_05732_amd as cg
+    from paper_1606_05732_amd import workloads as W
+    out = {}
+
+    def one(X, w, c, algo, elem):
+        plan = cg.SketchPlan(X, w.m, w.B, w.seed, algo=algo)
+        wall, stage, total, sx_stage = timed_steps(plan, steps, warmup, ev)
+        sx_bytes = (4 + elem) * c.nnz + 4 * (c.n + 1) + elem * w.B * c.d
+        ach = sx_bytes / (max(sx_stage, 1e-6) * 1e-3) / 1e9
+        log(f"algos: {w.name} {algo}: {wall:.4f} ms/step, S X stage {sx_stage * 1e3:.1f} us")
+        r = {"ms_per_step": round(wall, 4), "nnz_per_s": c.nnz / (wall * 1e-3)}
+        if algo != "rows":   # the rows route forms no S X: no stage of its own
+            r.update({"sx_stage_us": round(sx_stage * 1e3, 2), "sx_gbs": round(ach, 1),
+                      "sx_frac_hbm": round(ach / HBM_PEAK_GBS, 4)})
+        return r
+
+    c2 = w2.csr
+    out[w2.name] = {a: one(X2, w2, c2, a, 4) for a in ("binned", "atomic", "sorted", "rows")}
+    w1 = W.workload1()
+    c1 = w1.csr
+    X1 = cg.CsrMatrix(torch.from_numpy(c1.row_ptr).cuda(), torch.from_numpy(c1.col_idx).cuda(),
+                      torch.from_numpy(c1.vals).cuda(), c1.n, c1.d)
+    out[w1.name + "_fp64"] = {a: one(X1, w1, c1, a, 8) for a in ("auto", "sorted")}
+    return out
+
+
 def copy_calibration(mib=512, reps=3):
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters: run it under the same rocprofv3 --pmc pass as the
@@ -317,6 +351,8 @@ def main():
     ap.add_argument("--no-ladder", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--algos", action="store_true",
+                    help="also time every S X algorithm (and the FP64 CSR workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -391,6 +427,8 @@ def main():
                                              / MFMA_FP32_TFLOPS, 4),
                 "normals_per_launch": w.m * w.B},
     }
+    if args.algos:
+        result["algos"] = algos(max(5, args.steps // 2), 2, ev, X, w)
     del plan, X
     torch.cuda.empty_cache()
     if not args.no_ladder:
