@@ -47,50 +47,64 @@ __device__ __forceinline__ int d_row(int kq, int r) {
   return sizeof(T) == 8 ? kq + 4 * r : 4 * kq + r;
 }
 
-// One wavefront computes Z for 16 consecutive buckets b and up to 16 NB
-// columns.  MFMA roles: M = bucket (lane % 16), K = row i of G, N = column
-// of dY.  K slot kq of step s holds G row 4 (4 s + kq) + t for sub-step t,
-// so one Philox block (b, 4 s + kq) feeds the four sub-steps.  (dY is read
-// from memory -- it stays in the caches; staging it in LDS per workgroup
-// cost more occupancy than it saved.)
+// One wavefront computes Z for 16 MB consecutive buckets b (MB blocks of
+// 16) and up to 16 NB columns.  MFMA roles: M = bucket (lane % 16), K =
+// row i of G, N = column of dY.  K slot kq of step s holds G row
+// 4 (4 s + kq) + t for sub-step t, so one Philox block (b, 4 s + kq) feeds
+// the four sub-steps.  A step's dY values serve all MB bucket blocks.
+// (dY is read from memory -- it stays in the caches; staging it in LDS per
+// workgroup cost more occupancy than it saved.)
+constexpr int kGtMB = 2;
+
 template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void gt_dy_kernel(const T* __restrict__ dY, int m, int d,
                                                          int64_t B, Key key, T* __restrict__ Z) {
   using V = typename Vec4<T>::type;
+  constexpr int MB = kGtMB;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int bb = lane & 15, kq = lane >> 4;
   const int n0 = blockIdx.y * NB * 16;
-  const int64_t b0 = ((int64_t)blockIdx.x * kWaves + wave) * 16;
+  const int64_t b0 = ((int64_t)blockIdx.x * kWaves + wave) * 16 * MB;
   if (b0 >= B) return;
-  const int64_t b = b0 + bb;
-  V acc[NB];
+  V acc[MB][NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = V{0, 0, 0, 0};
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = V{0, 0, 0, 0};
   int col[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) col[nb] = n0 + nb * 16 + bb;
   const int steps = (m + 15) / 16;
   for (int s = 0; s < steps; ++s) {
     const int qq = 4 * s + kq;
-    T g[4] = {T(0), T(0), T(0), T(0)};
-    if (b < B && 4 * qq < m) box_muller(gauss_block((uint32_t)b, (uint32_t)qq, key.k0, key.k1), g);
+    T g[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int64_t b = b0 + 16 * mb + bb;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) g[mb][t] = T(0);
+      if (b < B && 4 * qq < m) box_muller(gauss_block((uint32_t)b, (uint32_t)qq, key.k0, key.k1), g[mb]);
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int i = 4 * qq + t;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const T y = (i < m && col[nb] < d) ? dY[(size_t)i * d + col[nb]] : T(0);
-        acc[nb] = mfma_k4(g[t], y, acc[nb]);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma_k4(g[mb][t], y, acc[mb][nb]);
       }
     }
   }
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = b0 + d_row<T>(kq, r);
-      if (row < B && col[nb] < d) Z[row * d + col[nb]] = acc[nb][r];
-    }
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = b0 + 16 * mb + d_row<T>(kq, r);
+        if (row < B && col[nb] < d) Z[row * d + col[nb]] = acc[mb][nb][r];
+      }
 }
 
 __device__ __forceinline__ void hash_rows_to_lds(uint32_t* sh, uint64_t g0, int nr, uint32_t B,
@@ -262,7 +276,7 @@ template <typename T>
 hipError_t launch_gt_dy(const T* dY, int m, int d, int64_t B, Key key, T* Z, hipStream_t s) {
   const int need = (d + 15) / 16;
   const int nb = need < 4 ? need : 4;
-  const unsigned gx = (unsigned)((B + 16 * kWaves - 1) / (16 * kWaves));
+  const unsigned gx = (unsigned)((B + 16 * kGtMB * kWaves - 1) / (16 * kGtMB * kWaves));
   const unsigned gy = (unsigned)((d + 16 * nb - 1) / (16 * nb));
   dim3 grid(gx, gy);
   switch (nb) {
