@@ -105,7 +105,8 @@ extern "C" {
                                fixed order (bitwise reproducible).  Draws m
                                normals per nonempty row instead of per
                                bucket: for X with few nonempty rows next to
-                               B (d^2 m buckets and sparse X)            */
+                               B (d^2 m buckets and sparse X).  kc is
+                               ignored                                   */
 
 /* ---- workspace kinds --------------------------------------------------- */
 #define CG_KIND_CSR 0
@@ -139,8 +140,11 @@ typedef struct cg_opts {
 } cg_opts;
 
 /* Forward stage boundaries recorded into cg_opts.stage_events:
- *   [0] before any work            [1] after S X is zeroed (atomic path)
- *   [2] after S X is complete      [3] after the split contraction
+ *   [0] before any work
+ *   [1] after the S X prologue: atomic, S X zeroed; binned, the per-tile
+ *       counts and their offsets; sorted and rows, right after [0]
+ *   [2] after S X is complete (rows: right after [1]; it forms no S X)
+ *   [3] after the split contraction (rows: its row partials)
  *   [4] after the fixed-order reduction (Y complete)                      */
 #define CG_STAGE_EVENTS 5
 
