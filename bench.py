@@ -25,6 +25,8 @@ Prints ONE JSON line on stdout (everything else goes to stderr):
                batch (built-in tuning table, then autotuned)
   adjoint      dX = T^T dY at the gradient workload's shape (n = 2^22,
                d = 64, m = 128, B = 2^19): time per call and its roofline
+  adjoint_csr  the gradient with respect to the stored values of the CSR
+               workload's X: time per call and its roofline
 """
 import argparse
 import ctypes
@@ -325,6 +327,38 @@ def algos(steps, warmup, ev, X2, w2):
     return out
 
 
+def adjoint_csr(steps, warmup, X, w):
+    """The CSR adjoint (the gradient with respect to the stored values,
+    dvals[k] = sigma(r) Z[h(r)][col_k]) on the FP32 CSR workload's matrix
+    and sketch: Z = G^T dY, then one gather per stored entry.  The
+    roofline counts the entries' reads (col_idx, row_ptr), the dvals
+    writes and one read of Z."""
+    import numpy as np
+    import torch
+
+    import paper_1606_05732_amd as cg
+    c = w.csr
+    dY = torch.from_numpy(np.random.default_rng(1002).standard_normal((w.m, c.d)).astype(np.float32)).cuda()
+    for _ in range(warmup):
+        cg.sketch_adjoint_csr(X, dY, w.m, w.B, w.seed)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        cg.sketch_adjoint_csr(X, dY, w.m, w.B, w.seed)
+    stop.record()
+    stop.synchronize()
+    t = start.elapsed_time(stop) / steps * 1e-3
+    nbytes = 8 * c.nnz + 4 * (c.n + 1) + 4 * w.B * c.d
+    achieved = nbytes / t / 1e9
+    log(f"adjoint csr: {t * 1e3:.3f} ms per call")
+    return {"workload": w.name, "ms_per_call": round(t * 1e3, 4),
+            "roofline": {"bound": "hbm", "kernel": "CSR adjoint (G^T dY, then the per-entry gather)",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes_per_launch": nbytes}}
+
+
 def copy_calibration(mib=512, reps=3):
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters: run it under the same rocprofv3 --pmc pass as the
@@ -429,6 +463,8 @@ def main():
     }
     if args.algos:
         result["algos"] = algos(max(5, args.steps // 2), 2, ev, X, w)
+    if not args.no_adjoint:
+        result["adjoint_csr"] = adjoint_csr(max(5, args.steps // 2), 2, X, w)
     del plan, X
     torch.cuda.empty_cache()
     if not args.no_ladder:
