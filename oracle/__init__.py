@@ -13,15 +13,22 @@ matrices materialised where that makes the definition visible.
 Parity status per function (what pins it against something other than
 itself is listed in tests/test_oracle_*.py):
   philox4x32_10      pinned: published known-answer vectors (Salmon et al.)
-  hash_rows          pinned: structure of S (Section 2), uniformity and
+  hash_rows          pinned: structure of S (Section 1.1), uniformity and
                      collision statistics, Lemma lb worked identity (Sec. 7)
   gaussian_block     pinned: Box-Muller radius/angle identities, KS vs the
                      normal CDF, bound, nesting
   sketch_*           pinned: brute-force dense product, injective special
                      case, closed-form E||M-C||_F^2, covariance over seeds,
                      conditional whitening KS (Theorem 1 setting)
-  adjoint_*          pinned: adjoint identity and central differences
+  sx_csr, csr_to_dense, sketch_csr
+                     pinned also against scipy.sparse's own CSR expansion
+                     and sparse product S @ X
+  sketch_touched     pinned: equals the full product (brute force, scatter)
+  adjoint_*          pinned: adjoint identity and central differences;
+                     adjoint_csr also against scipy.sparse S^T Z
   quantise_bf16/fp8  pinned: torch CPU dtype conversions (library routines)
-  emulate_reduced    parity unpinned (a diagnostic; no external reference)
+  emulate_reduced    pinned: a hand-worked BF16 / E4M3 case (ties to even,
+                     the 448 edge, subnormals, 128-row blocks, the G scale),
+                     each expected value derived from the format definitions
 """
 from .countgauss import *  # noqa: F401,F403

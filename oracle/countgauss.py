@@ -40,7 +40,7 @@ __all__ = [
     "philox4x32_10", "seed_key", "hash_words", "hash_rows",
     "uniforms_from_words", "box_muller", "gaussian_block", "gaussian_matrix",
     "dense_gaussian_block", "countsketch_matrix", "row_of_nonzero",
-    "sx_dense", "sx_csr", "sketch_dense", "sketch_csr", "csr_to_dense",
+    "sx_dense", "sx_csr", "sketch_dense", "sketch_csr", "sketch_touched", "csr_to_dense",
     "adjoint_dense", "adjoint_csr", "central_fd", "round_to_format",
     "quantise_bf16", "quantise_fp8_e4m3", "fp8_block_exponent",
     "emulate_reduced", "rel_frobenius", "GAUSS_ABS_MAX",
@@ -242,6 +242,21 @@ def sketch_dense(X, m, B, seed, row_offset=0, method="scatter"):
     raise ValueError(method)
 
 
+def sketch_touched(X, m, B, seed, row_offset=0):
+    """Y = sum over the rows r of sigma(r) G[:, h(r)] X[r, :] (the streamed
+    formulation of G.S.X, Section 1.1: S puts row r into column h(r) of
+    S.X with sign sigma(r)), with only the columns of G that some row
+    hashes to generated: for B far larger than n.  FP64."""
+    X = np.asarray(X, dtype=np.float64)
+    n, d = X.shape
+    h, sigma = hash_rows(seed, B, np.arange(n, dtype=np.uint64) + np.uint64(row_offset))
+    Y = np.zeros((m, d))
+    for b in np.unique(h):
+        rows = h == b
+        Y += gaussian_block(seed, m, int(b), 1) @ (sigma[rows] @ X[rows])[None, :]
+    return Y
+
+
 def sketch_csr(row_ptr, col_idx, vals, n, d, m, B, seed, row_offset=0):
     """Y = G.S.X (m x d, FP64) for CSR X, via the O(nnz) scatter."""
     return _sketch_from_sx(sx_csr(row_ptr, col_idx, vals, n, d, seed, B, row_offset),
@@ -325,7 +340,8 @@ def emulate_reduced(G, SX, precision, kblock=128):
     "fp8") per 128-wide block along B; FP64 accumulation.  For fp8 each SX
     block gets the power-of-two scale 2^fp8_block_exponent(amax) and G the
     constant 2^-6 (|G| <= 5.77 < 7).  Inputs are first rounded to FP32, as
-    the GPU holds them.  Diagnostic only (the paper fixes no precision)."""
+    the GPU holds them.  The paper fixes no precision: this is the reading
+    the reduced-precision contraction follows."""
     G32 = np.asarray(G, np.float32).astype(np.float64)
     S32 = np.asarray(SX, np.float32).astype(np.float64)
     m, B = G32.shape

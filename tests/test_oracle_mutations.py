@@ -110,3 +110,106 @@ def test_transposed_gaussian_is_caught(monkeypatch):
     _patch(monkeypatch, "gaussian_block", transposed)
     with pytest.raises(AssertionError):
         R.test_box_muller_pairs_share_a_radius_and_carry_the_angle()
+
+
+def test_off_by_one_hash_word_is_caught(monkeypatch):
+    def shifted(seed, rows):
+        rows = np.asarray(rows, dtype=np.uint64)
+        q = rows >> np.uint64(2)
+        ctr = np.zeros(rows.shape + (4,), dtype=np.uint32)
+        ctr[..., 0] = (q & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        ctr[..., 1] = (q >> np.uint64(32)).astype(np.uint32)
+        out = OC.philox4x32_10(ctr, OC.seed_key(seed))
+        lane = ((rows + np.uint64(1)) & np.uint64(3)).astype(np.int64)
+        return np.take_along_axis(out, lane[..., None], axis=-1)[..., 0]
+
+    _patch(monkeypatch, "hash_words", shifted)
+    with pytest.raises(AssertionError):
+        R.test_hash_uses_one_philox_block_per_four_rows()
+
+
+def test_uniform_map_without_midpoint_is_caught(monkeypatch):
+    def bad(w):
+        w = np.asarray(w, dtype=np.uint32)
+        return (w >> np.uint32(8)).astype(np.float64) * 2.0 ** -24
+
+    _patch(monkeypatch, "uniforms_from_words", bad)
+    with pytest.raises(AssertionError):
+        R.test_uniform_map_is_open_interval_and_exact()
+
+
+def test_transposed_gaussian_counter_is_caught(monkeypatch):
+    # counter (q, b, 1, 0) instead of (b, q, 1, 0)
+    def transposed(seed, m, b0, nb):
+        nq = (m + 3) // 4
+        ctr = np.zeros((nq, nb, 4), dtype=np.uint32)
+        ctr[..., 0] = np.arange(nq, dtype=np.uint32)[:, None]
+        ctr[..., 1] = np.arange(b0, b0 + nb, dtype=np.uint32)[None, :]
+        ctr[..., 2] = 1
+        z = OC.box_muller(OC.philox4x32_10(ctr, OC.seed_key(seed)))
+        return np.transpose(z, (0, 2, 1)).reshape(nq * 4, nb)[:m]
+
+    _patch(monkeypatch, "gaussian_block", transposed)
+    with pytest.raises(AssertionError):
+        R.test_box_muller_pairs_share_a_radius_and_carry_the_angle()
+
+
+# ---- emulate_reduced: each planted mistake fails the hand-worked case ----
+def _emulate_variant(kblock=128, g_scale=2.0 ** -6, exponent=None, rescale=True):
+    def emulate(G, SX, precision, kblock_=kblock):
+        G32 = np.asarray(G, np.float32).astype(np.float64)
+        S32 = np.asarray(SX, np.float32).astype(np.float64)
+        m, B = G32.shape
+        Y = np.zeros((m, S32.shape[1]))
+        for k0 in range(0, B, kblock):
+            g = G32[:, k0:k0 + kblock]
+            s = S32[k0:k0 + kblock]
+            if precision == "bf16":
+                Y += OC.quantise_bf16(g) @ OC.quantise_bf16(s)
+                continue
+            amax = np.max(np.abs(s)) if s.size else 0.0
+            e = exponent(amax) if exponent else OC.fp8_block_exponent(amax)
+            sx = 2.0 ** e
+            P = OC.quantise_fp8_e4m3(g / g_scale) @ OC.quantise_fp8_e4m3(s / sx)
+            Y += P * (g_scale * sx) if rescale else P
+        return Y
+    return emulate
+
+
+def _e_minus_8_everywhere(amax):
+    if amax == 0.0:
+        return 0
+    import math
+    return math.frexp(amax)[1] - 8
+
+
+@pytest.mark.parametrize("variant", [
+    dict(kblock=64), dict(exponent=_e_minus_8_everywhere), dict(g_scale=2.0 ** -5),
+    dict(g_scale=2.0 ** -7), dict(rescale=False)],
+    ids=["block64", "e_minus_8", "g_scale_2^-5", "g_scale_2^-7", "no_rescale"])
+def test_emulate_reduced_mistakes_are_caught(monkeypatch, variant):
+    import tests.test_oracle_quant as Q
+    # the unmutated function passes the worked case ...
+    Q.test_emulate_reduced_worked_case()
+    # ... and each mutation fails it
+    _patch(monkeypatch, "emulate_reduced", _emulate_variant(**variant))
+    with pytest.raises(AssertionError):
+        Q.test_emulate_reduced_worked_case()
+
+
+def test_shifted_row_of_nonzero_is_caught_by_scipy_cross_check(monkeypatch):
+    # every stored entry attributed to the row after its own (the last row's
+    # entries wrap to row 0): S X and the CSR adjoint must then disagree
+    # with scipy.sparse's own CSR expansion
+    orig = OC.row_of_nonzero
+
+    def shifted(row_ptr):
+        r = orig(row_ptr)
+        n = len(row_ptr) - 1
+        return (r + 1) % max(n, 1)
+
+    _patch(monkeypatch, "row_of_nonzero", shifted)
+    with pytest.raises(AssertionError):
+        S.test_csr_oracle_matches_scipy_sparse_product()
+    with pytest.raises(AssertionError):
+        S.test_csr_adjoint_matches_scipy_sparse_transpose()

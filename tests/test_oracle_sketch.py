@@ -191,3 +191,61 @@ def test_adjoint_matches_central_differences():
     grad = X.T @ O.adjoint_dense(2 * O.sketch_dense(r, m, B, seed), n, 1, m, B, seed)[:, 0]
     fdw = O.central_fd(lambda W: lw(W[0]), w[None, :], [(0, c) for c in range(d)], 1e-3)
     assert np.allclose(fdw, grad, rtol=1e-7)
+
+
+def _scipy_countsketch(seed, B, n, row_offset=0):
+    # S (B x n) as a scipy.sparse matrix straight from the hash: column r
+    # holds sigma(r) at row h(r)
+    from scipy import sparse
+    h, sigma = O.hash_rows(seed, B, np.arange(n, dtype=np.uint64) + np.uint64(row_offset))
+    return sparse.csr_matrix((sigma, (h, np.arange(n))), shape=(B, n))
+
+
+def _csr_cases():
+    rng = _rng(11)
+    yield csr_bernoulli(rng, 3000, 17, 0.05, dtype=np.float64), 3000, 17, 500, 0
+    yield csr_bernoulli(rng, 1000, 64, 0.3, dtype=np.float64, absolute=True), 1000, 64, 4096, 5
+    # empty rows at both ends and duplicate columns inside a row
+    rp = np.array([0, 0, 3, 3, 6, 6], np.int32)
+    ci = np.array([1, 1, 2, 0, 2, 2], np.int32)
+    v = np.array([1.5, -2.0, 0.25, 3.0, -1.0, 4.0])
+    yield (rp, ci, v), 5, 3, 7, 2 ** 33 + 1
+
+
+def test_csr_oracle_matches_scipy_sparse_product():
+    # S X with scipy.sparse doing the CSR expansion and the product, none of
+    # the oracle's own CSR handling involved
+    from scipy import sparse
+    for (rp, ci, v), n, d, B, off in _csr_cases():
+        seed = 40 + n
+        Xs = sparse.csr_matrix((v, ci, rp), shape=(n, d))
+        ref = (_scipy_countsketch(seed, B, n, off) @ Xs).toarray()
+        got = O.sx_csr(rp, ci, v, n, d, seed, B, row_offset=off)
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
+        assert np.allclose(O.csr_to_dense(rp, ci, v, n, d), Xs.toarray(), rtol=0, atol=0)
+        y = O.sketch_csr(rp, ci, v, n, d, 6, B, seed, row_offset=off)
+        assert np.allclose(y, O.gaussian_matrix(seed, 6, B) @ ref, rtol=1e-12, atol=1e-12)
+
+
+def test_csr_adjoint_matches_scipy_sparse_transpose():
+    # dvals[k] = (S^T Z)[row of k, col_idx[k]], rows from scipy's expansion
+    from scipy import sparse
+    for (rp, ci, v), n, d, B, off in _csr_cases():
+        seed, m = 90 + n, 5
+        dY = _rng(n).standard_normal((m, d))
+        Z = O.gaussian_matrix(seed, m, B).T @ dY
+        dense_grad = np.asarray(_scipy_countsketch(seed, B, n, off).T @ Z)
+        coo = sparse.csr_matrix((np.arange(1, len(v) + 1, dtype=np.float64), ci, rp),
+                                shape=(n, d)).tocoo()
+        order = np.argsort(coo.data)         # back to stored-entry order
+        ref = dense_grad[coo.row[order], coo.col[order]]
+        got = O.adjoint_csr(rp, ci, dY, n, d, m, B, seed, row_offset=off)
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_touched_columns_formulation_matches_the_full_product():
+    # generating only the columns of G that rows hash to changes nothing
+    X = _rng(12).standard_normal((200, 4))
+    for B, off in ((50, 0), (3000, 7), (1 << 20, 2 ** 33 + 2)):
+        ref = O.sketch_dense(X, 9, B, 606, row_offset=off, method="brute" if B < 5000 else "scatter")
+        assert O.rel_frobenius(O.sketch_touched(X, 9, B, 606, row_offset=off), ref) < 1e-13
