@@ -212,6 +212,28 @@ int cg_sketch_adjoint_csr(const int32_t* row_ptr, const int32_t* col_idx,
                           int64_t d, int64_t m, int64_t B, uint64_t seed,
                           void* dvals, const cg_opts* opts);
 
+/* ---- allocation-free forward -------------------------------------------- *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, meaning and result as cg_sketch_csr, but the workspace is a
+ * static device buffer of CG_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends (opts->workspace and
+ * opts->workspace_bytes are ignored; opts may be NULL).  Nothing is
+ * allocated or freed.  A call whose workspace (cg_workspace_bytes with kind
+ * CG_KIND_CSR) exceeds the buffer fails with CG_ENOSPACE before anything is
+ * queued.  Every call on one GPU shares that GPU's buffer: calls that can
+ * overlap on one GPU (different streams, or threads without ordering) race
+ * and give undefined results; calls queued on one stream are ordered.  The
+ * buffer's contents on entry do not matter (every kernel writes what it
+ * reads first).  The first call on a device looks up that device's buffer
+ * address (hipGetSymbolAddress) with that device current.                */
+#define CG_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+int cg_sketch_csr_noalloc(const int32_t* row_ptr, const int32_t* col_idx,
+                          const void* vals, int dtype, int64_t n, int64_t d,
+                          int64_t nnz, int64_t m, int64_t B, uint64_t seed,
+                          void* Y, const cg_opts* opts);
+
 /* ---- many independent instances in one batch ----------------------------- *
  * Independent CSR transforms, each with its own n, d, m, B and seed (FP32,
  * native precision), computed together: each phase of the transform (S X

@@ -8,5 +8,5 @@ device memory and streams.
 """
 from .api import (BatchedSketch, CsrMatrix, CountGaussFn, countgauss, debug_gaussian,  # noqa: F401
                   debug_hash, debug_philox, get_tuning, set_tuning, sketch, sketch_adjoint,
-                  sketch_adjoint_csr, sketch_batched, SketchPlan)
+                  sketch_adjoint_csr, sketch_batched, sketch_csr_noalloc, SketchPlan)
 from ._lib import CountGaussError, LIB_PATH  # noqa: F401

@@ -19,7 +19,7 @@ EXPORTS = [
     "cg_opts_init", "cg_version", "cg_status_string", "cg_last_error",
     "cg_workspace_bytes", "cg_sketch_csr", "cg_sketch_dense", "cg_sketch_adjoint",
     "cg_sketch_adjoint_csr", "cg_batched_plan", "cg_sketch_batched", "cg_set_tuning",
-    "cg_get_tuning",
+    "cg_get_tuning", "cg_sketch_csr_noalloc",
     "cg_debug_philox", "cg_debug_hash", "cg_debug_gaussian",
 ]
 
@@ -40,6 +40,9 @@ class CgOpts(ctypes.Structure):
 
 
 CG_STAGE_EVENTS = 5
+
+# size of the static scratch buffer behind cg_sketch_csr_noalloc
+CG_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class CgInstance(ctypes.Structure):
@@ -114,6 +117,8 @@ def load():
                                               ctypes.POINTER(_SZ)]),
         "cg_sketch_csr": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _I64, _I64,
                                          _U64, _P, ctypes.POINTER(CgOpts)]),
+        "cg_sketch_csr_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _I64,
+                                                 _I64, _U64, _P, ctypes.POINTER(CgOpts)]),
         "cg_sketch_dense": (ctypes.c_int, [_P, _I64, ctypes.c_int, _I64, _I64, _I64, _I64, _U64,
                                            _P, ctypes.POINTER(CgOpts)]),
         "cg_sketch_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I64, _I64, _I64, _I64, _U64, _P,

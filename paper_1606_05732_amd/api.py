@@ -202,6 +202,30 @@ def countgauss(X, m, B, seed, row_offset=0):
     return CountGaussFn.apply(X, m, B, seed, row_offset)
 
 
+def sketch_csr_noalloc(X, m, B, seed, row_offset=0, out=None):
+    """Y = T X for CSR X through cg_sketch_csr_noalloc: the library's static
+    device scratch replaces the workspace, so the call allocates nothing
+    beyond Y (none at all when `out`, an m x d tensor of X's dtype, is
+    given).  Calls that can overlap on one GPU race on that scratch."""
+    lib = L.load()
+    csr = _as_csr(X)
+    if csr is None:
+        raise TypeError("sketch_csr_noalloc takes a CSR matrix")
+    _require_cuda(csr.row_ptr, csr.col_idx, csr.vals)
+    code = _dtype_code(csr.vals)
+    Y = out if out is not None else torch.empty((m, csr.d), dtype=csr.vals.dtype,
+                                                device=csr.vals.device)
+    if Y.shape != (m, csr.d) or Y.dtype != csr.vals.dtype or not Y.is_contiguous():
+        raise ValueError("out must be a contiguous m x d tensor of X's dtype")
+    opts = L.make_opts(L.CG_PREC_NATIVE, L.CG_SX_AUTO, 0, _stream(csr.vals.device), None, 0,
+                       row_offset)
+    L.check(lib.cg_sketch_csr_noalloc(_ptr(csr.row_ptr), _ptr(csr.col_idx), _ptr(csr.vals), code,
+                                      csr.n, csr.d, csr.nnz, m, B,
+                                      ctypes.c_uint64(seed & (2 ** 64 - 1)), _ptr(Y),
+                                      ctypes.byref(opts)), "cg_sketch_csr_noalloc")
+    return Y
+
+
 # ---- test access to the random source ----------------------------------
 def debug_philox(seed, ctr):
     """Philox4x32-10 of each row of ctr (int32/uint32-valued tensor k x 4)."""

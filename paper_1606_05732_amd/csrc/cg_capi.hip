@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "countgauss.h"
@@ -415,6 +416,73 @@ int cg_sketch_adjoint_csr(const int32_t* row_ptr, const int32_t* col_idx, int64_
   }
   if (e != hipSuccess) return hip_fail(e, "adjoint (CSR)");
   return CG_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free forward (CSR) --------------------------------------
+// Its workspace is this file-scope device array: every GPU the library runs
+// on holds one copy until the process ends.  In host code the name is only
+// a stand-in for the symbol; the device address of each GPU's copy comes
+// from hipGetSymbolAddress with that GPU current, once, and only that
+// address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[CG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(CG_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+    if (!p || ((uintptr_t)p & 255)) return fail(CG_EHIP, "static scratch has no 256-byte aligned address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cg_sketch_csr_noalloc(const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                          int dtype, int64_t n, int64_t d, int64_t nnz, int64_t m, int64_t B,
+                          uint64_t seed, void* Y, const cg_opts* opts) {
+  Opts o;
+  int st = read_opts(opts, &o);
+  if (st) return st;
+  if ((st = check_shape(dtype, n, d, m, B, o))) return st;
+  if (nnz < 0) return fail(CG_EINVAL, "nnz = %lld < 0", (long long)nnz);
+  if (nnz > 0x7fffffffLL) return fail(CG_EUNSUPPORTED, "nnz = %lld >= 2^31 with int32 indices", (long long)nnz);
+  if (!row_ptr || !Y || (nnz > 0 && (!col_idx || !vals)))
+    return fail(CG_EINVAL, "null pointer argument");
+  if (o.sx_algo == CG_SX_SORTED && n > 0x7fffffffLL)
+    return fail(CG_EUNSUPPORTED, "sorted S X needs n < 2^31");
+  const FwdLayout L = forward_layout(dtype, true, n, d, nnz, m, B, o);
+  if (L.algo < 0) return algo_fail(L.algo, true);
+  if (L.total > (size_t)CG_NOALLOC_SCRATCH_BYTES)
+    return fail(CG_ENOSPACE, "this call needs %zu bytes of scratch; the static buffer holds %zu",
+                L.total, (size_t)CG_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((st = scratch_of_current_device(&ws))) return st;
+  o.workspace = ws;
+  o.workspace_bytes = (size_t)CG_NOALLOC_SCRATCH_BYTES;
+  if (dtype == CG_DTYPE_F64)
+    return forward_typed<double>(row_ptr, col_idx, (const double*)vals, 0, true, n, d, nnz, m, B,
+                                 seed, (double*)Y, o, L);
+  return forward_typed<float>(row_ptr, col_idx, (const float*)vals, 0, true, n, d, nnz, m, B, seed,
+                              (float*)Y, o, L);
 }
 
 int cg_debug_philox(uint64_t seed, const uint32_t* ctr, int64_t count, uint32_t* out,

@@ -127,3 +127,27 @@ def test_debug_entry_points_validate():
     _err(lib.cg_debug_hash(1, 0, 0, 10, FAKE, FAKE, None), "B =")
     _err(lib.cg_debug_gaussian(1, 0, 0, 10, 0, FAKE, None), "m =")
     _err(lib.cg_debug_philox(1, FAKE, -1, FAKE, None), "count")
+
+
+def test_noalloc_rejects_what_the_static_buffer_cannot_hold():
+    lib = L.load()
+    o = L.make_opts()
+    # the FP32-at-scale CSR workload needs far more than the static buffer
+    need = ctypes.c_size_t(0)
+    L.check(lib.cg_workspace_bytes(L.CG_KIND_CSR, L.CG_DTYPE_F32, 1 << 24, 32, 64, 65536,
+                                   27_000_000, ctypes.byref(o), ctypes.byref(need)), "ws")
+    assert need.value > L.CG_NOALLOC_SCRATCH_BYTES
+    st = lib.cg_sketch_csr_noalloc(FAKE, FAKE, FAKE, L.CG_DTYPE_F32, 1 << 24, 32, 27_000_000, 64,
+                                   65536, 1, FAKE, ctypes.byref(o))
+    assert _err(st, "static buffer") == L.CG_ENOSPACE
+    # the usual argument checks come first, and opts may be NULL
+    st = lib.cg_sketch_csr_noalloc(FAKE, FAKE, FAKE, L.CG_DTYPE_F32, 0, 4, 10, 4, 4, 1, FAKE, None)
+    assert _err(st, "n =") == L.CG_EINVAL
+    st = lib.cg_sketch_csr_noalloc(None, FAKE, FAKE, L.CG_DTYPE_F32, 10, 4, 10, 4, 4, 1, FAKE, None)
+    assert _err(st, "null") == L.CG_EINVAL
+
+
+def test_noalloc_buffer_size_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define CG_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == L.CG_NOALLOC_SCRATCH_BYTES
