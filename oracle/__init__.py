@@ -30,5 +30,18 @@ itself is listed in tests/test_oracle_*.py):
   emulate_reduced    pinned: a hand-worked BF16 / E4M3 case (ties to even,
                      the 448 edge, subnormals, 128-row blocks, the G scale),
                      each expected value derived from the format definitions
+  gaussian_product_* pinned: 2-stability (entries N(0, ||x_j||^2), squared
+                     norms chi-square m), row covariance X^T X, scipy.sparse
+                     product with the explicit G~, chunk / offset invariance
+  row_extrema        pinned: hand-worked fixture with ties and NaNs
+                     (tests/golden/row_extrema.txt), numpy argmax/argmin
+  *_anchors          pinned: on separable data every unique extremum is an
+                     anchor (extreme points of the polytope, Section 4)
+  lowerbound.*       pinned: KL against quadrature and Monte Carlo (scipy
+                     densities), Pinsker against exact TV, hand-worked pair
+                     statistic, chi-square law under G~, the lemma's
+                     unique-collision identity, E||I-M||_F^2 by Monte Carlo
 """
 from .countgauss import *  # noqa: F401,F403
+from .anchors import *  # noqa: F401,F403
+from . import lowerbound  # noqa: F401

@@ -39,7 +39,8 @@ __all__ = [
     "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1",
     "philox4x32_10", "seed_key", "hash_words", "hash_rows",
     "uniforms_from_words", "box_muller", "gaussian_block", "gaussian_matrix",
-    "dense_gaussian_block", "countsketch_matrix", "row_of_nonzero",
+    "dense_gaussian_block", "dense_gaussian_columns", "gaussian_product_dense",
+    "gaussian_product_csr", "countsketch_matrix", "row_of_nonzero",
     "sx_dense", "sx_csr", "sketch_dense", "sketch_csr", "sketch_touched", "csr_to_dense",
     "adjoint_dense", "adjoint_csr", "central_fd", "round_to_format",
     "quantise_bf16", "quantise_fp8_e4m3", "fp8_block_exponent",
@@ -150,18 +151,66 @@ def gaussian_matrix(seed, m, B):
     return gaussian_block(seed, m, 0, B)
 
 
-def dense_gaussian_block(seed, m, r0, nr):
-    """Columns [r0, r0+nr) of the m x n dense Gaussian G~ (tag 2), FP64."""
+def dense_gaussian_block(seed, m, r0, nr, q0=0):
+    """Columns [r0, r0+nr) of the m x n dense Gaussian G~ (tag 2), FP64;
+    rows 4 q0 .. m-1 only when q0 > 0."""
     nq = (m + 3) // 4
     r = np.arange(r0, r0 + nr, dtype=np.uint64)
-    q = np.arange(nq, dtype=np.uint64)
+    q = np.arange(q0, nq, dtype=np.uint64)
+    nq -= q0
     ctr = np.zeros((nq, nr, 4), dtype=np.uint32)
     ctr[..., 0] = (r & _MASK32).astype(np.uint32)[None, :]
     ctr[..., 1] = q[:, None].astype(np.uint32)
     ctr[..., 2] = 2
     ctr[..., 3] = (r >> np.uint64(32)).astype(np.uint32)[None, :]
     z = box_muller(philox4x32_10(ctr, seed_key(seed)))
-    return np.transpose(z, (0, 2, 1)).reshape(nq * 4, nr)[:m]
+    return np.transpose(z, (0, 2, 1)).reshape(nq * 4, nr)[:m - 4 * q0]
+
+
+def dense_gaussian_columns(seed, m, rows):
+    """Columns `rows` (global row indices of X, any order) of the m x n
+    dense Gaussian G~ (tag 2), FP64 (m, len(rows))."""
+    nq = (m + 3) // 4
+    r = np.asarray(rows, dtype=np.uint64)
+    q = np.arange(nq, dtype=np.uint64)
+    ctr = np.zeros((nq, len(r), 4), dtype=np.uint32)
+    ctr[..., 0] = (r & _MASK32).astype(np.uint32)[None, :]
+    ctr[..., 1] = q[:, None].astype(np.uint32)
+    ctr[..., 2] = 2
+    ctr[..., 3] = (r >> np.uint64(32)).astype(np.uint32)[None, :]
+    z = box_muller(philox4x32_10(ctr, seed_key(seed)))
+    return np.transpose(z, (0, 2, 1)).reshape(nq * 4, len(r))[:m]
+
+
+def gaussian_product_dense(X, m, seed, row_offset=0, chunk=1 << 15):
+    """G~ X (m x d, FP64): the dense Gaussian projection that T X stands in
+    for (Section 1.1, "Our Results": O(nnz(X) m) time; Theorem 1 compares the
+    distributions of G S U and G~ U).  Row chunks of X times the matching
+    columns of G~."""
+    X = np.asarray(X, dtype=np.float64)
+    n, d = X.shape
+    Y = np.zeros((m, d))
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        Y += dense_gaussian_block(seed, m, row_offset + r0, r1 - r0) @ X[r0:r1]
+    return Y
+
+
+def gaussian_product_csr(row_ptr, col_idx, vals, n, d, m, seed, row_offset=0, chunk=1 << 15):
+    """G~ X for CSR X (m x d, FP64): only the columns of G~ of nonempty rows
+    contribute."""
+    row = row_of_nonzero(row_ptr)
+    col = np.asarray(col_idx, np.int64)
+    v = np.asarray(vals, np.float64)
+    rows = np.unique(row)
+    Y = np.zeros((m, d))
+    for k0 in range(0, len(rows), chunk):
+        sel = rows[k0:k0 + chunk]
+        Xs = np.zeros((len(sel), d))
+        mask = (row >= sel[0]) & (row <= sel[-1])
+        np.add.at(Xs, (np.searchsorted(sel, row[mask]), col[mask]), v[mask])
+        Y += dense_gaussian_columns(seed, m, sel.astype(np.uint64) + np.uint64(row_offset)) @ Xs
+    return Y
 
 
 def countsketch_matrix(seed, B, n, row_offset=0):

@@ -164,3 +164,30 @@ def workload5(count=512, m=32, seed=1005, scale=1.0):
         rp, ci, v = csr_bernoulli(rng, n, d, p, dtype=np.float32, absolute=True)
         out.append(Workload(f"batched_{len(out)}", m, B, s, csr=CsrInput(rp, ci, v, n, d)))
     return out
+
+
+def separable_nmf(rng, features, points, k, dtype=np.float64):
+    """A k-separable nonnegative matrix (the exact-recovery experiment of the
+    paper's Section 6): X = U V^T, features x points, with U (features x k)
+    i.i.d. uniform on [0, 1] and V (points x k) holding the identity in its
+    first k rows and i.i.d. uniform [0, 1] entries below, every row of V
+    scaled to unit l1 norm, so that every column of X is a convex
+    combination of its first k columns (the anchors).  Returns (X, anchors)."""
+    U = rng.uniform(0.0, 1.0, size=(features, k))
+    V = np.empty((points, k))
+    V[:k] = np.eye(k)
+    V[k:] = rng.uniform(0.0, 1.0, size=(points - k, k))
+    V /= V.sum(axis=1, keepdims=True)
+    return (U @ V.T).astype(dtype), np.arange(k)
+
+
+def block_orthonormal(d, L, dtype=np.float64):
+    """The matrix U of the lower-bound lemma (Section 7) as CSR: n = L d rows,
+    d columns, column i holding the value 1/sqrt(L) in rows L i .. L i + L - 1
+    (disjoint blocks, so the columns are orthonormal).  Every row has exactly
+    one stored entry.  Returns (row_ptr, col_idx, vals, n)."""
+    n = L * d
+    row_ptr = np.arange(n + 1, dtype=np.int32)
+    col_idx = (np.arange(n) // L).astype(np.int32)
+    vals = np.full(n, 1.0 / np.sqrt(L), dtype=dtype)
+    return row_ptr, col_idx, vals, n

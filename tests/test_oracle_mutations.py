@@ -213,3 +213,69 @@ def test_shifted_row_of_nonzero_is_caught_by_scipy_cross_check(monkeypatch):
         S.test_csr_oracle_matches_scipy_sparse_product()
     with pytest.raises(AssertionError):
         S.test_csr_adjoint_matches_scipy_sparse_transpose()
+
+
+# ---- the dense Gaussian product, Algorithm 1 and Section 7 quantities ----
+import oracle.anchors as OA  # noqa: E402
+import oracle.lowerbound as OL  # noqa: E402
+import tests.test_oracle_anchors as A  # noqa: E402
+import tests.test_oracle_gaussian as GQ  # noqa: E402
+import tests.test_oracle_lowerbound as LBT  # noqa: E402
+
+
+def test_gaussian_product_csr_dropping_the_last_row_is_caught(monkeypatch):
+    orig = OC.gaussian_product_csr
+
+    def dropped(row_ptr, col_idx, vals, n, d, m, seed, row_offset=0, chunk=1 << 15):
+        rp = np.array(row_ptr, copy=True)
+        k = int(rp[-2])
+        return orig(rp[:-1], col_idx[:k], vals[:k], n - 1, d, m, seed, row_offset, chunk)
+
+    _patch(monkeypatch, "gaussian_product_csr", dropped)
+    with pytest.raises(AssertionError):
+        GQ.test_csr_form_matches_scipy_sparse_product()
+
+
+def test_gaussian_product_with_half_variance_is_caught(monkeypatch):
+    orig = OC.gaussian_product_dense
+
+    def halved(X, m, seed, row_offset=0, chunk=1 << 15):
+        return orig(X, m, seed, row_offset, chunk) * np.sqrt(0.5)
+
+    _patch(monkeypatch, "gaussian_product_dense", halved)
+    with pytest.raises(AssertionError):
+        GQ.test_squared_norm_is_chi_square_m()
+
+
+def test_row_extrema_taking_the_last_tie_is_caught(monkeypatch):
+    def last_tie(Z):
+        Z = np.asarray(Z, dtype=np.float64)
+        m, d = Z.shape
+        rev = Z[:, ::-1]
+        return (d - 1 - np.argmax(rev, axis=1)), (d - 1 - np.argmin(rev, axis=1))
+
+    monkeypatch.setattr(OA, "row_extrema", last_tie)
+    monkeypatch.setattr(O, "row_extrema", last_tie)
+    with pytest.raises(AssertionError):
+        A.test_row_extrema_hand_worked_fixture()
+
+
+def test_kl_without_log_determinant_is_caught(monkeypatch):
+    def no_logdet(M):
+        w = np.linalg.eigvalsh(np.asarray(M, dtype=np.float64))
+        return 0.5 * (float(np.sum(1.0 / w)) - len(w))
+
+    monkeypatch.setattr(OL, "kl_to_standard", no_logdet)
+    with pytest.raises(AssertionError):
+        LBT.test_kl_matches_quadrature_in_one_dimension()
+
+
+def test_pair_statistic_against_m_instead_of_2m_is_caught(monkeypatch):
+    def wrong(Y, m):
+        P = OL.pair_norms(Y)
+        vals = P[np.isfinite(P)]
+        return float(np.max(np.abs(vals - m))) if vals.size else 0.0
+
+    monkeypatch.setattr(OL, "pair_deviation", wrong)
+    with pytest.raises(AssertionError):
+        LBT.test_pair_deviation_hand_worked()
