@@ -89,9 +89,11 @@ extern "C" {
                                wavefront: bitwise reproducible             */
 #define CG_SX_BINNED 3      /* FP32 only: split by bucket range, each range
                                summed in LDS by one workgroup.  CSR sums are
-                               64-bit fixed point with a per-range scale from
-                               the range's max |x| (bitwise reproducible;
-                               entries below max|x| * 2^-(61 - log2 count)
+                               two-word 64-bit fixed point with a per-range
+                               scale from the range's max |x| (bitwise
+                               reproducible; every cell keeps FP32 precision
+                               for entries down to about
+                               max|x| * 2^-(100 - 2 log2 count), smaller ones
                                lose precision); dense rows are summed in FP32
                                (order varies from run to run)              */
 #define CG_SX_ROWS 4        /* FP32 CSR data, native precision, no sx_out:
@@ -107,12 +109,25 @@ extern "C" {
                                bucket: for X with few nonempty rows next to
                                B (d^2 m buckets and sparse X).  kc is
                                ignored                                   */
+#define CG_SX_FUSED 5       /* FP32 CSR data, native precision, no sx_out:
+                               the binned split, then one workgroup per
+                               bucket range sums the range's S X slice in
+                               LDS (as BINNED) and multiplies it at once by
+                               the columns of G of those buckets, so S X
+                               never reaches memory; the per-range partial
+                               products are added in range order (bitwise
+                               reproducible).  kc is ignored            */
 
 /* ---- workspace kinds --------------------------------------------------- */
 #define CG_KIND_CSR 0
 #define CG_KIND_DENSE 1
 #define CG_KIND_ADJOINT 2
 #define CG_KIND_ADJOINT_CSR 3
+#define CG_KIND_GAUSSIAN_DENSE 4   /* cg_gaussian_dense (B ignored)    */
+#define CG_KIND_GAUSSIAN_CSR 5     /* cg_gaussian_csr (B ignored)      */
+#define CG_KIND_ANCHORS_COUNTGAUSS 6   /* cg_anchors_dense, T X        */
+#define CG_KIND_ANCHORS_GAUSSIAN 7     /* cg_anchors_dense, G~ X       */
+#define CG_KIND_LEMMA 8                /* cg_lemma_stats (n ignored)   */
 
 typedef struct cg_opts {
   uint32_t struct_size;     /* sizeof(cg_opts)                             */
@@ -211,6 +226,81 @@ int cg_sketch_adjoint_csr(const int32_t* row_ptr, const int32_t* col_idx,
                           int64_t nnz, const void* dY, int dtype, int64_t n,
                           int64_t d, int64_t m, int64_t B, uint64_t seed,
                           void* dvals, const cg_opts* opts);
+
+/* ---- the dense Gaussian product T X stands in for --------------------- *
+ * Y~ = G~ X, with G~ an m x n matrix of i.i.d. unit-variance Gaussians:
+ * the projection whose distribution T X matches (Theorem 1 compares G S U
+ * with G~ U) and whose cost, O(nnz(X) m), T X avoids (Section 1.1, "Our
+ * Results"; the paper's comparison projection "RG").  G~ is generated in
+ * registers, never stored: G~[i][r] for the global row r = row_offset +
+ * local row is Box-Muller of the Philox words of counter
+ * (lo32(r), i >> 2, 2, hi32(r)), entry i & 3 (same key and u mapping as G).
+ * The contraction runs on MFMA, split over the rows of X with the partial
+ * products added in a fixed order (bitwise reproducible).
+ *   dense:  X device dtype, n rows of stride ldx >= d; FP32 or FP64.
+ *   CSR:    as cg_sketch_csr; FP32 only (only nonempty rows draw normals).
+ *   Y       device dtype[m*d], overwritten.
+ * n < 2^31; precision must be NATIVE; workspace of at least
+ * cg_workspace_bytes(CG_KIND_GAUSSIAN_DENSE / _CSR, ...) bytes (B is
+ * ignored there).  Errors as for cg_sketch_csr.                          */
+int cg_gaussian_dense(const void* X, int64_t ldx, int dtype, int64_t n,
+                      int64_t d, int64_t m, uint64_t seed, void* Y,
+                      const cg_opts* opts);
+int cg_gaussian_csr(const int32_t* row_ptr, const int32_t* col_idx,
+                    const void* vals, int dtype, int64_t n, int64_t d,
+                    int64_t nnz, int64_t m, uint64_t seed, void* Y,
+                    const cg_opts* opts);
+
+/* ---- Algorithm 1: anchor extraction for separable NMF ------------------ *
+ * Section 4 ("CountGauss NMF"): with X features x points (the anchors are
+ * columns), form Z = T X and take, for every row of Z, the column where it
+ * is largest (I_max) and smallest (I_min).  Every unique extremum names an
+ * anchor of separable X (a linear function over a polytope is extremal at
+ * a vertex).  The paper is silent on ties: the lowest column index wins;
+ * NaN entries never win and a row without a number gives -1.             */
+
+/* Row extrema of Z (device dtype, m rows of stride ldz >= d): imax[i],
+ * imin[i] (device int32[m]).  stream: hipStream_t.                       */
+int cg_row_extrema(const void* Z, int dtype, int64_t m, int64_t d,
+                   int64_t ldz, int32_t* imax, int32_t* imin, void* stream);
+
+#define CG_PROJ_COUNTGAUSS 0   /* Z = T X (Algorithm 1)                    */
+#define CG_PROJ_GAUSSIAN 1     /* Z = G~ X (the Gaussian baseline the paper
+                                  compares with, "GP" in Section 6; B unused) */
+
+/* Algorithm 1 on dense X (n x d, row stride ldx; n = features, d = points):
+ * Z = T X (proj CG_PROJ_COUNTGAUSS, same options as cg_sketch_dense) or
+ * Z = G~ X (CG_PROJ_GAUSSIAN), then its row extrema into imax, imin
+ * (device int32[m]).  Z lives in the workspace: at least
+ * cg_workspace_bytes(CG_KIND_ANCHORS_COUNTGAUSS / _GAUSSIAN, ...) bytes.
+ * opts->stage_events is ignored.  Errors as for cg_sketch_dense.         */
+int cg_anchors_dense(const void* X, int64_t ldx, int dtype, int64_t n,
+                     int64_t d, int64_t m, int64_t B, uint64_t seed, int proj,
+                     int32_t* imax, int32_t* imin, const cg_opts* opts);
+
+/* ---- Section 7 diagnostics --------------------------------------------- *
+ * For U (n x d, orthonormal columns, d <= 64), from Y = T U or G~ U
+ * (device dtype[m*d]) and optionally S U (device dtype[B*d], e.g. the
+ * sx_out of the forward call; NULL = not given), into stats (device
+ * double[6]):
+ *   [0] max over i < j of | ||Y (e_i + e_j)||^2 - 2 m |: the statistic of
+ *       the lower-bound lemma, which a unique collision between the blocks
+ *       of two columns moves by about 2 m / L;
+ *   [1] ||I - M||_F^2 with M = (S U)^T (S U), the covariance of every row
+ *       of T U given S (O(d^2 / B) in expectation, proof of Theorem 1);
+ *   [2] KL(N(0, I) || N(0, M)) = 1/2 tr(M^-1 - I) + 1/2 ln det M (the claim
+ *       on Gaussian KL divergences; +inf if M is singular);
+ *   [3] Pinsker's bound min(1, sqrt(m KL / 2)) on the total variation
+ *       between the m rows of T U given S and those of G~ U;
+ *   [4] the number of pairs i < j with |M_ij| > 1e-9 (1 after a unique
+ *       collision between two columns' blocks);
+ *   [5] 1 if M is positive definite, else 0.
+ * [1] .. [5] are NaN when SU is NULL.  Gram matrices are summed in FP64 in
+ * a fixed order.  Workspace: cg_workspace_bytes(CG_KIND_LEMMA, dtype, -,
+ * d, m, B, ...).  Errors: CG_EINVAL, CG_EUNSUPPORTED (d > 64),
+ * CG_ENOSPACE, CG_EHIP.                                                  */
+int cg_lemma_stats(const void* Y, const void* SU, int dtype, int64_t m,
+                   int64_t B, int64_t d, double* stats, const cg_opts* opts);
 
 /* ---- allocation-free forward -------------------------------------------- *
  * For callers that cannot allocate device memory: code under HIP graph
@@ -315,6 +405,17 @@ int cg_set_tuning(const int32_t* rows_per_item, const int32_t* kc_per_item,
 int cg_get_tuning(int32_t* rows_per_item, int32_t* kc_per_item, int32_t classes);
 
 /* ---- test access to the random source ---------------------------------- */
+
+/* Memory ceilings for the rooflines: a device copy of `bytes` (src to
+ * dst), a read of src (dst receives 2048 uint32 checksums), or a write of
+ * dst, with 16-byte accesses on consecutive addresses over 2048
+ * workgroups.  bytes: a positive multiple of 16; pointers 16-byte aligned
+ * device memory.  stream: hipStream_t.                                    */
+#define CG_STREAM_COPY 0
+#define CG_STREAM_READ 1
+#define CG_STREAM_WRITE 2
+int cg_debug_stream(int kind, const void* src, void* dst, int64_t bytes,
+                    void* stream);
 
 /* out[4k..4k+3] = Philox4x32-10(counter ctr[4k..4k+3], key(seed)) for
  * k < count.  ctr, out: device uint32 arrays.  stream: hipStream_t. */

@@ -11,15 +11,21 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcountgau
 CG_OK, CG_EINVAL, CG_ENOSPACE, CG_EUNSUPPORTED, CG_EHIP = 0, 1, 2, 3, 4
 CG_DTYPE_F32, CG_DTYPE_F64 = 0, 1
 CG_PREC_NATIVE, CG_PREC_BF16, CG_PREC_FP8 = 0, 1, 2
-CG_SX_AUTO, CG_SX_ATOMIC, CG_SX_SORTED, CG_SX_BINNED, CG_SX_ROWS = 0, 1, 2, 3, 4
+CG_SX_AUTO, CG_SX_ATOMIC, CG_SX_SORTED, CG_SX_BINNED, CG_SX_ROWS, CG_SX_FUSED = 0, 1, 2, 3, 4, 5
 CG_KIND_CSR, CG_KIND_DENSE, CG_KIND_ADJOINT, CG_KIND_ADJOINT_CSR = 0, 1, 2, 3
+CG_KIND_GAUSSIAN_DENSE, CG_KIND_GAUSSIAN_CSR = 4, 5
+CG_KIND_ANCHORS_COUNTGAUSS, CG_KIND_ANCHORS_GAUSSIAN = 6, 7
+CG_PROJ_COUNTGAUSS, CG_PROJ_GAUSSIAN = 0, 1
+CG_KIND_LEMMA = 8
+CG_STREAM_COPY, CG_STREAM_READ, CG_STREAM_WRITE = 0, 1, 2
 
 # Every function declared in include/countgauss.h.
 EXPORTS = [
     "cg_opts_init", "cg_version", "cg_status_string", "cg_last_error",
     "cg_workspace_bytes", "cg_sketch_csr", "cg_sketch_dense", "cg_sketch_adjoint",
     "cg_sketch_adjoint_csr", "cg_batched_plan", "cg_sketch_batched", "cg_set_tuning",
-    "cg_get_tuning", "cg_sketch_csr_noalloc",
+    "cg_get_tuning", "cg_sketch_csr_noalloc", "cg_gaussian_dense", "cg_gaussian_csr",
+    "cg_row_extrema", "cg_anchors_dense", "cg_lemma_stats", "cg_debug_stream",
     "cg_debug_philox", "cg_debug_hash", "cg_debug_gaussian",
 ]
 
@@ -119,6 +125,15 @@ def load():
                                          _U64, _P, ctypes.POINTER(CgOpts)]),
         "cg_sketch_csr_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _I64,
                                                  _I64, _U64, _P, ctypes.POINTER(CgOpts)]),
+        "cg_gaussian_dense": (ctypes.c_int, [_P, _I64, ctypes.c_int, _I64, _I64, _I64, _U64, _P,
+                                             ctypes.POINTER(CgOpts)]),
+        "cg_gaussian_csr": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _I64, _U64,
+                                           _P, ctypes.POINTER(CgOpts)]),
+        "cg_lemma_stats": (ctypes.c_int, [_P, _P, ctypes.c_int, _I64, _I64, _I64, _P,
+                                          ctypes.POINTER(CgOpts)]),
+        "cg_row_extrema": (ctypes.c_int, [_P, ctypes.c_int, _I64, _I64, _I64, _P, _P, _P]),
+        "cg_anchors_dense": (ctypes.c_int, [_P, _I64, ctypes.c_int, _I64, _I64, _I64, _I64, _U64,
+                                            ctypes.c_int, _P, _P, ctypes.POINTER(CgOpts)]),
         "cg_sketch_dense": (ctypes.c_int, [_P, _I64, ctypes.c_int, _I64, _I64, _I64, _I64, _U64,
                                            _P, ctypes.POINTER(CgOpts)]),
         "cg_sketch_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I64, _I64, _I64, _I64, _U64, _P,
@@ -131,6 +146,7 @@ def load():
                                              ctypes.POINTER(CgOpts)]),
         "cg_set_tuning": (ctypes.c_int, [ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I32]),
         "cg_get_tuning": (ctypes.c_int, [ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I32]),
+        "cg_debug_stream": (ctypes.c_int, [ctypes.c_int, _P, _P, _I64, _P]),
         "cg_debug_philox": (ctypes.c_int, [_U64, _P, _I64, _P, _P]),
         "cg_debug_hash": (ctypes.c_int, [_U64, _I64, _U64, _I64, _P, _P, _P]),
         "cg_debug_gaussian": (ctypes.c_int, [_U64, _I64, _I64, _I64, ctypes.c_int, _P, _P]),

@@ -14,7 +14,7 @@ from . import _lib as L
 _PREC = {"native": L.CG_PREC_NATIVE, "fp32": L.CG_PREC_NATIVE, "fp64": L.CG_PREC_NATIVE,
          "bf16": L.CG_PREC_BF16, "fp8": L.CG_PREC_FP8}
 _ALGO = {"auto": L.CG_SX_AUTO, "atomic": L.CG_SX_ATOMIC, "sorted": L.CG_SX_SORTED,
-         "binned": L.CG_SX_BINNED, "rows": L.CG_SX_ROWS}
+         "binned": L.CG_SX_BINNED, "rows": L.CG_SX_ROWS, "fused": L.CG_SX_FUSED}
 
 
 @dataclass
@@ -84,9 +84,11 @@ def sketch(X, m, B, seed, precision="native", algo="auto", row_offset=0, kc=0, s
     """Y = T X = G (S X) (m x d) for dense X (n x d, unit column stride) or
     CSR X (CsrMatrix or torch.sparse_csr).  precision: native (FP32/FP64),
     bf16 or fp8 inputs to the G (S X) contraction.  algo: auto, atomic,
-    sorted (bitwise reproducible), binned S X, or rows (FP32 CSR, native
-    precision: no S X, Y summed over the nonempty rows).  sx_out: optional
-    B x d tensor that receives S X (not with rows)."""
+    sorted (bitwise reproducible), binned S X, rows (FP32 CSR, native
+    precision: no S X, Y summed over the nonempty rows) or fused (FP32 CSR,
+    native precision: each bucket range's S X summed in LDS and contracted
+    at once, never written).  sx_out: optional B x d tensor that receives
+    S X (not with rows or fused)."""
     lib = L.load()
     prec = _PREC[precision]
     sx_algo = _ALGO[algo]
@@ -133,6 +135,124 @@ def sketch(X, m, B, seed, precision="native", algo="auto", row_offset=0, kc=0, s
         L.check(st, "cg_sketch_dense")
     del buf
     return Y
+
+
+def gaussian(X, m, seed, row_offset=0, kc=0):
+    """Y~ = G~ X (m x d) with G~ an m x n Gaussian generated in registers:
+    the dense Gaussian projection that T X stands in for.  Dense X (FP32 or
+    FP64) or CSR X (FP32)."""
+    lib = L.load()
+    csr = _as_csr(X)
+    if csr is not None:
+        _require_cuda(csr.row_ptr, csr.col_idx, csr.vals)
+        device, dt, n, d = csr.vals.device, csr.vals.dtype, csr.n, csr.d
+        kind, nnz = L.CG_KIND_GAUSSIAN_CSR, csr.nnz
+    else:
+        if not isinstance(X, torch.Tensor) or X.dim() != 2:
+            raise TypeError("X must be a 2-D dense tensor or a CSR matrix")
+        _require_cuda(X)
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        device, dt, (n, d) = X.device, X.dtype, X.shape
+        kind, nnz = L.CG_KIND_GAUSSIAN_DENSE, 0
+    code = _dtype_code(torch.empty(0, dtype=dt))
+    Y = torch.empty((m, d), dtype=dt, device=device)
+    opts = L.make_opts(L.CG_PREC_NATIVE, L.CG_SX_AUTO, kc, _stream(device), None, 0, row_offset)
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.cg_workspace_bytes(kind, code, n, d, m, 1, nnz, ctypes.byref(opts),
+                                   ctypes.byref(nbytes)), "cg_workspace_bytes")
+    buf, addr, size = _workspace(nbytes.value, device)
+    opts.workspace, opts.workspace_bytes = addr, size
+    sd = ctypes.c_uint64(seed & (2 ** 64 - 1))
+    if csr is not None:
+        L.check(lib.cg_gaussian_csr(_ptr(csr.row_ptr), _ptr(csr.col_idx), _ptr(csr.vals), code, n, d,
+                                    nnz, m, sd, _ptr(Y), ctypes.byref(opts)), "cg_gaussian_csr")
+    else:
+        L.check(lib.cg_gaussian_dense(_ptr(X), X.stride(0), code, n, d, m, sd, _ptr(Y),
+                                      ctypes.byref(opts)), "cg_gaussian_dense")
+    del buf
+    return Y
+
+
+def row_extrema(Z):
+    """Step 3 of Algorithm 1: for every row of Z (m x d), the lowest column
+    of its largest and of its smallest value (int32 tensors imax, imin; NaNs
+    never win, -1 for a row of NaNs)."""
+    lib = L.load()
+    _require_cuda(Z)
+    if Z.dim() != 2:
+        raise TypeError("Z must be 2-D")
+    if Z.stride(1) != 1:
+        Z = Z.contiguous()
+    m, d = Z.shape
+    imax = torch.empty(m, dtype=torch.int32, device=Z.device)
+    imin = torch.empty(m, dtype=torch.int32, device=Z.device)
+    L.check(lib.cg_row_extrema(_ptr(Z), _dtype_code(Z), m, d, Z.stride(0), _ptr(imax), _ptr(imin),
+                               _stream(Z.device)), "cg_row_extrema")
+    return imax, imin
+
+
+def anchors(X, m, B, seed, projection="countgauss"):
+    """Algorithm 1 (CountGauss NMF) on dense X (features x points): the row
+    extrema (imax, imin) of Z = T X, or of Z = G~ X with
+    projection="gaussian" (the Gaussian baseline; B unused)."""
+    lib = L.load()
+    _require_cuda(X)
+    if X.dim() != 2:
+        raise TypeError("X must be 2-D")
+    if X.stride(1) != 1:
+        X = X.contiguous()
+    n, d = X.shape
+    proj = {"countgauss": L.CG_PROJ_COUNTGAUSS, "gaussian": L.CG_PROJ_GAUSSIAN}[projection]
+    kind = L.CG_KIND_ANCHORS_COUNTGAUSS if proj == L.CG_PROJ_COUNTGAUSS else L.CG_KIND_ANCHORS_GAUSSIAN
+    code = _dtype_code(X)
+    imax = torch.empty(m, dtype=torch.int32, device=X.device)
+    imin = torch.empty(m, dtype=torch.int32, device=X.device)
+    opts = L.make_opts(L.CG_PREC_NATIVE, L.CG_SX_AUTO, 0, _stream(X.device))
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.cg_workspace_bytes(kind, code, n, d, m, max(B, 1), 0, ctypes.byref(opts),
+                                   ctypes.byref(nbytes)), "cg_workspace_bytes")
+    buf, addr, size = _workspace(nbytes.value, X.device)
+    opts.workspace, opts.workspace_bytes = addr, size
+    L.check(lib.cg_anchors_dense(_ptr(X), X.stride(0), code, n, d, m, max(B, 1),
+                                 ctypes.c_uint64(seed & (2 ** 64 - 1)), proj, _ptr(imax), _ptr(imin),
+                                 ctypes.byref(opts)), "cg_anchors_dense")
+    del buf
+    return imax, imin
+
+
+LEMMA_STATS = ("pair_deviation", "frobenius_gap", "kl", "tv_pinsker_bound", "offdiag_pairs",
+               "positive_definite")
+
+
+def lemma_stats(Y, SU=None):
+    """Section 7 statistics of Y = T U (or G~ U), m x d, and optionally
+    S U (B x d), for U with orthonormal columns (d <= 64): a float64 tensor
+    of 6 values on the device, named by LEMMA_STATS (all but the first NaN
+    without S U)."""
+    lib = L.load()
+    _require_cuda(Y)
+    Y = Y.contiguous()
+    m, d = Y.shape
+    B = 1
+    if SU is not None:
+        _require_cuda(SU)
+        if SU.dtype != Y.dtype or SU.dim() != 2 or SU.shape[1] != d:
+            raise ValueError("SU must be B x d with Y's dtype")
+        SU = SU.contiguous()
+        B = SU.shape[0]
+    code = _dtype_code(Y)
+    out = torch.empty(6, dtype=torch.float64, device=Y.device)
+    opts = L.make_opts(L.CG_PREC_NATIVE, L.CG_SX_AUTO, 0, _stream(Y.device))
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.cg_workspace_bytes(L.CG_KIND_LEMMA, code, 1, d, m, B, 0, ctypes.byref(opts),
+                                   ctypes.byref(nbytes)), "cg_workspace_bytes")
+    buf, addr, size = _workspace(nbytes.value, Y.device)
+    opts.workspace, opts.workspace_bytes = addr, size
+    L.check(lib.cg_lemma_stats(_ptr(Y), _ptr(SU), code, m, B, d, _ptr(out), ctypes.byref(opts)),
+            "cg_lemma_stats")
+    del buf
+    return out
 
 
 def sketch_adjoint(dY, n, m, B, seed, row_offset=0, out=None):
@@ -197,8 +317,35 @@ class CountGaussFn(torch.autograd.Function):
         return dX, None, None, None, None
 
 
+class CountGaussCsrFn(torch.autograd.Function):
+    """Y = T X for CSR X as a function of its stored values: backward is
+    dvals[k] = sigma(r) (G^T dY)[h(r), col_idx[k]] for the entry k of row r
+    (T is linear, so this is <dY, T X>'s gradient).  The sparsity pattern,
+    m, B, seed and row_offset are not differentiable."""
+
+    @staticmethod
+    def forward(ctx, vals, row_ptr, col_idx, n, d, m, B, seed, row_offset=0):
+        X = CsrMatrix(row_ptr, col_idx, vals, n, d)
+        ctx.save_for_backward(row_ptr, col_idx)
+        ctx.n, ctx.d, ctx.m, ctx.B, ctx.seed, ctx.row_offset = n, d, m, B, seed, row_offset
+        return sketch(X, m, B, seed, row_offset=row_offset)
+
+    @staticmethod
+    def backward(ctx, dY):
+        row_ptr, col_idx = ctx.saved_tensors
+        X = CsrMatrix(row_ptr, col_idx, dY.new_empty(0), ctx.n, ctx.d)
+        dvals = sketch_adjoint_csr(X, dY, ctx.m, ctx.B, ctx.seed, ctx.row_offset)
+        return dvals, None, None, None, None, None, None, None, None
+
+
 def countgauss(X, m, B, seed, row_offset=0):
-    """Differentiable T X for dense X (autograd through CountGaussFn)."""
+    """Differentiable T X (autograd through CountGaussFn for dense X; for
+    CSR X -- a CsrMatrix or torch.sparse_csr tensor -- through
+    CountGaussCsrFn, with respect to the stored values)."""
+    csr = _as_csr(X)
+    if csr is not None:
+        return CountGaussCsrFn.apply(csr.vals, csr.row_ptr, csr.col_idx, csr.n, csr.d, m, B, seed,
+                                     row_offset)
     return CountGaussFn.apply(X, m, B, seed, row_offset)
 
 

@@ -127,10 +127,22 @@ constexpr int red_elems() {
 
 // `red`: red_elems<T, NB>() elements of LDS for the cross-wavefront sum.
 // HALF: the group holds at most 32 rows of G (see the file comment).
-template <typename T, int NB, bool HALF>
-__device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64_t B, int d, int m,
-                                                 int kc, Key key, T* __restrict__ part, int64_t bx,
-                                                 int group, int ng, T* red) {
+// Normals of K column k (of B for G, TAG 1; a row of X, offset by col0, for
+// the dense Gaussian G~, TAG 2), row quad q.
+template <int TAG>
+__device__ __forceinline__ Words4 k_block(int64_t k, uint64_t col0, uint32_t q, Key key) {
+  if constexpr (TAG == 1) return gauss_block((uint32_t)k, q, key.k0, key.k1);
+  return dense_gauss_block(col0 + (uint64_t)k, q, key.k0, key.k1);
+}
+
+// TAG 1: Y = G (S X) with SX the B x d matrix S X (ld = d).  TAG 2: the
+// dense Gaussian product G~ X, the same contraction with X (n x d, row
+// stride ld) in place of S X and G~'s columns col0 + k in place of G's.
+template <typename T, int NB, bool HALF, int TAG = 1>
+__device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64_t ld, uint64_t col0,
+                                                 int64_t B, int d, int m, int kc, Key key,
+                                                 T* __restrict__ part, int64_t bx, int group,
+                                                 int ng, T* red) {
   using V = typename Vec4<T>::type;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = lane & 15, kq = lane >> 4;
@@ -164,7 +176,7 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
       const int64_t b = kg + 4 * u + kq;
       const int64_t cb = b < kend ? b : kend - 1;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x[u][nb] = SX[cb * d + ccol[nb]];
+      for (int nb = 0; nb < NB; ++nb) x[u][nb] = SX[cb * ld + ccol[nb]];
     }
   };
   // (unconditional: indices clamp to kend - 1 >= 0, and the group after
@@ -185,7 +197,7 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
         const int64_t bg = kg + 4 * (u + (p >> 3)) + kq;
         const bool gok = bg < kend;
         T g[4];
-        box_muller(gauss_block((uint32_t)(gok ? bg : kend - 1), q, key.k0, key.k1), g);
+        box_muller(k_block<TAG>(gok ? bg : kend - 1, col0, q, key), g);
         T a0[4], a1[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -213,7 +225,7 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
         const bool bok = b < kend;
         const int64_t cb = bok ? b : kend - 1;
         T g[4];
-        box_muller(gauss_block((uint32_t)cb, q, key.k0, key.k1), g);
+        box_muller(k_block<TAG>(cb, col0, q, key), g);
 #pragma unroll
         for (int t = 0; t < 4; ++t) g[t] = bok ? g[t] : T(0);
         T xv[NB];
@@ -229,15 +241,18 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
   block_reduce_store<T, NB, V>(acc, red, wave, lane, group, n0, m, d, part + (size_t)bx * m * d);
 }
 
-template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restrict__ SX, int64_t B,
-                                                              int d, int m, int kc, Key key,
+template <typename T, int NB, int TAG>
+__global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restrict__ SX, int64_t ld,
+                                                              uint64_t col0, int64_t B, int d, int m,
+                                                              int kc, Key key,
                                                               T* __restrict__ part) {
   __shared__ T red[red_elems<T, NB>()];
   if (half_group(m, (int)blockIdx.y))
-    gsx_native_block<T, NB, true>(SX, B, d, m, kc, key, part, blockIdx.x, blockIdx.y, blockIdx.z, red);
+    gsx_native_block<T, NB, true, TAG>(SX, ld, col0, B, d, m, kc, key, part, blockIdx.x, blockIdx.y,
+                                       blockIdx.z, red);
   else
-    gsx_native_block<T, NB, false>(SX, B, d, m, kc, key, part, blockIdx.x, blockIdx.y, blockIdx.z, red);
+    gsx_native_block<T, NB, false, TAG>(SX, ld, col0, B, d, m, kc, key, part, blockIdx.x,
+                                        blockIdx.y, blockIdx.z, red);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -292,14 +307,37 @@ __device__ __forceinline__ int cvt_fp8(float a, float b, int old) {
   return __builtin_amdgcn_cvt_pk_fp8_f32(a, b, old, HI);
 }
 
+// Power-of-two scales of the FP8 contraction, one pair per 128-row block of
+// S X (all d columns): (2^-e, 2^(e - 6)) with e the smallest integer such
+// that the block's largest |value| is at most 448 2^e (NaNs ignored), at
+// least -100 so that 2^-e stays finite.  One wavefront per block, 16-byte
+// loads with eight in flight; the contraction then reads one pair per
+// block instead of the block itself.
+__global__ __launch_bounds__(kThreads) void fp8_block_scale_kernel(const float* __restrict__ SX,
+                                                                   int64_t B, int d,
+                                                                   float2* __restrict__ scale) {
+  const int64_t blk = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t nblk = (B + 127) / 128;
+  if (blk >= nblk) return;
+  const int64_t r0 = blk * 128;
+  const int64_t rows = min((int64_t)128, B - r0);
+  const float amax = wave_max(block_amax(SX + r0 * d, rows * d, lane));
+  const int e = max(fp8_block_exponent(amax), -100);
+  if (lane == 0) scale[blk] = make_float2(ldexpf(1.0f, -e), ldexpf(1.0f, e - 6));
+}
+
 // Reduced-precision inputs: BF16 (round to nearest even) or FP8 E4M3 with
-// one power-of-two scale per 128-wide block of B for S X and 2^-6 for G;
-// FP32 accumulation.  K = 32 per MFMA: lane (p, kq) supplies the eight
-// columns b = base + 8 kq + e, e = 0..7, i.e. eight Philox blocks per step.
+// one power-of-two scale per 128-wide block of B for S X (from
+// fp8_block_scale_kernel) and 2^-6 for G; FP32 accumulation.  K = 32 per
+// MFMA: lane (p, kq) supplies the eight columns b = base + 8 kq + e,
+// e = 0..7, i.e. eight Philox blocks per step.  A step's S X values are
+// loaded one step ahead, so their latency hides behind the step before.
 template <int NB, bool FP8>
 __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restrict__ SX,
                                                             int64_t B, int d, int m, int kc,
-                                                            Key key, float* __restrict__ part) {
+                                                            Key key, const float2* __restrict__ bscale,
+                                                            float* __restrict__ part) {
   constexpr int KBLK = FP8 ? 128 : 32;
   __shared__ float red[3 * 16 * NB * 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -321,18 +359,25 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
 
   const int64_t kbeg = ((int64_t)blockIdx.x * kWaves + wave) * kc;
   const int64_t kend = min(kbeg + (int64_t)kc, B);
+  // this lane's eight S X rows of the step at `base`, clamped (values past
+  // the chunk or the columns are zeroed where they are used)
+  auto load_step = [&](int64_t base, float (&x)[8][NB]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t b = base + e;
+      const int64_t c = b < kend ? b : kend - 1;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) x[e][nb] = SX[c * d + ccol[nb]];
+    }
+  };
+  float xn[8][NB];
+  load_step(kbeg + kq * 8, xn);
   for (int64_t kb = kbeg; kb < kend; kb += KBLK) {
     float xscale = 1.0f, yscale = 1.0f;
     if constexpr (FP8) {
-      // block amax over rows [kb, kb + 128) and all d columns of S X:
-      // 16-byte loads, eight in flight per lane, when the block is aligned
-      const int64_t rows = min((int64_t)KBLK, kend - kb);
-      const float amax = wave_max(block_amax(SX + kb * d, rows * d, lane));
-      // blocks with amax below 448 * 2^-100 keep the scale 2^100 so that
-      // 2^-e stays finite in FP32
-      const int e = max(fp8_block_exponent(amax), -100);
-      xscale = ldexpf(1.0f, -e);
-      yscale = ldexpf(1.0f, e - 6);
+      const float2 sc = bscale[kb >> 7];
+      xscale = sc.x;
+      yscale = sc.y;
     }
     // FP8 block products are rescaled before they join the accumulator;
     // BF16 needs no scale and accumulates directly
@@ -344,9 +389,16 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
 #pragma unroll
     for (int sub = 0; sub < KBLK / 32; ++sub) {
       const int64_t base = kb + sub * 32 + kq * 8;
+      float x[8][NB];
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) x[e][nb] = xn[e][nb];
+      // the next step's rows (the step after the last is a harmless reload)
+      load_step(base + 32, xn);
       // operands packed as they are produced, two columns of B at a time;
-      // loads and normals unguarded at clamped indices, values past the
-      // chunk or the columns zeroed
+      // normals unguarded at clamped indices, values past the chunk or the
+      // columns zeroed
       int glo[4] = {0, 0, 0, 0}, ghi[4] = {0, 0, 0, 0};
       int xlo[NB], xhi[NB];
       v8bf gb[4], xb[NB];
@@ -361,19 +413,14 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
         box_muller(gauss_block((uint32_t)c0, q, key.k0, key.k1), z0);
         box_muller(gauss_block((uint32_t)c1, q, key.k0, key.k1), z1);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          x0[nb] = SX[c0 * d + ccol[nb]];
-          x1[nb] = SX[c1 * d + ccol[nb]];
-        }
-#pragma unroll
         for (int t = 0; t < 4; ++t) {
           z0[t] = ok0 ? z0[t] : 0.0f;
           z1[t] = ok1 ? z1[t] : 0.0f;
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          x0[nb] = ok0 && col[nb] < d ? x0[nb] : 0.0f;
-          x1[nb] = ok1 && col[nb] < d ? x1[nb] : 0.0f;
+          x0[nb] = ok0 && col[nb] < d ? x[e][nb] : 0.0f;
+          x1[nb] = ok1 && col[nb] < d ? x[e + 1][nb] : 0.0f;
         }
         if constexpr (FP8) {
           // columns e, e + 1 go to byte pair (e / 2) % 2 of word e / 4
@@ -509,7 +556,11 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int NB, bool HALF>
+// TAG 1: the rows of G (S X) as above.  TAG 2: the dense Gaussian product
+// G~ X, summed the same way over the nonempty rows r with column r of G~
+// (global row row_offset + r, no sign) in place of sigma(r) G[:, h(r)]; the
+// compacted row records then hold the local row index instead of the hash.
+template <int NB, bool HALF, int TAG = 1>
 __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int group, int ng,
                                               float* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -545,7 +596,12 @@ __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int 
 #pragma unroll
     for (int j = 1; j < 5; ++j) rp[j] = max(rp[j], rp[j - 1]);
     uint32_t hv[4] = {0u, 0u, 0u, 0u};
-    if (rl < w1) hash4(a.row_offset + (uint64_t)rl, (uint32_t)a.B, a.key.k0, a.key.k1, hv);
+    if constexpr (TAG == 1) {
+      if (rl < w1) hash4(a.row_offset + (uint64_t)rl, (uint32_t)a.B, a.key.k0, a.key.k1, hv);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) hv[j] = (uint32_t)(rl + j);
+    }
     // compaction in row order: the rank of row (lane, j) is the number of
     // nonempty rows of lower lanes plus this lane's before j
     uint64_t mk[4];
@@ -625,8 +681,14 @@ __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int 
         const bool ok = e < eN;
         const uint32_t hp = ok ? rh[e] : 0u;
         float g[4];
-        box_muller(gauss_block(hash_bucket(hp), q, a.key.k0, a.key.k1), g);
-        const float sg = ok ? (hash_negative(hp) ? -1.0f : 1.0f) : 0.0f;
+        float sg;
+        if constexpr (TAG == 1) {
+          box_muller(gauss_block(hash_bucket(hp), q, a.key.k0, a.key.k1), g);
+          sg = ok ? (hash_negative(hp) ? -1.0f : 1.0f) : 0.0f;
+        } else {
+          box_muller(dense_gauss_block(a.row_offset + (uint64_t)hp, q, a.key.k0, a.key.k1), g);
+          sg = ok ? 1.0f : 0.0f;
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) g[t] *= sg;
 #pragma unroll
@@ -652,13 +714,13 @@ __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int 
                                      a.part + (size_t)bx * m * d);
 }
 
-template <int NB>
+template <int NB, int TAG>
 __global__ __launch_bounds__(kThreads) void gx_rows_kernel(GsxArgs a) {
   __shared__ __align__(16) float lds[rows_lds_elems<NB>()];
   if (half_group(a.m, (int)blockIdx.y))
-    gx_rows_block<NB, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+    gx_rows_block<NB, true, TAG>(a, blockIdx.x, blockIdx.y, blockIdx.z, lds);
   else
-    gx_rows_block<NB, false>(a, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+    gx_rows_block<NB, false, TAG>(a, blockIdx.x, blockIdx.y, blockIdx.z, lds);
 }
 
 // Batched forms: item -> instance from the item table; the local index is
@@ -687,9 +749,11 @@ __global__ __launch_bounds__(kThreads) void gsx_batched_kernel(const GsxArgs* __
     else
       gx_rows_block<NB, false>(a, bx, group, ng, red);
   } else if (half) {
-    gsx_native_block<float, NB, true>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
+    gsx_native_block<float, NB, true>(a.SX, a.d, 0, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng,
+                                      red);
   } else {
-    gsx_native_block<float, NB, false>(a.SX, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group, ng, red);
+    gsx_native_block<float, NB, false>(a.SX, a.d, 0, a.B, a.d, a.m, a.kc, a.key, a.part, bx, group,
+                                       ng, red);
   }
 }
 
@@ -702,18 +766,26 @@ __global__ __launch_bounds__(64 * kRedWaves) void splitk_batched_kernel(
                              (int64_t)blockIdx.x - first[i]);
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int TAG = 1>
 void launch_native(const GsxPlan& pl, const T* SX, int64_t B, int d, int m, Key key, T* part,
-                   hipStream_t s) {
+                   hipStream_t s, int64_t ld = -1, uint64_t col0 = 0) {
   dim3 grid((unsigned)pl.parts, (unsigned)pl.mgroups, (unsigned)pl.ngroups);
-  gsx_native_kernel<T, NB><<<grid, kThreads, 0, s>>>(SX, B, d, m, pl.kc, key, part);
+  gsx_native_kernel<T, NB, TAG><<<grid, kThreads, 0, s>>>(SX, ld < 0 ? (int64_t)d : ld, col0, B, d,
+                                                           m, pl.kc, key, part);
 }
 
 template <int NB, bool FP8>
 void launch_lowp(const GsxPlan& pl, const float* SX, int64_t B, int d, int m, Key key,
-                 float* part, hipStream_t s) {
+                 float2* bscale, float* part, hipStream_t s, bool scales_ready = false) {
+  if constexpr (FP8) {
+    if (!scales_ready) {
+    const int64_t nblk = (B + 127) / 128;
+    fp8_block_scale_kernel<<<(unsigned)((nblk + kWaves - 1) / kWaves), kThreads, 0, s>>>(SX, B, d,
+                                                                                      bscale);
+    }
+  }
   dim3 grid((unsigned)pl.parts, (unsigned)pl.mgroups, (unsigned)pl.ngroups);
-  gsx_lowp_kernel<NB, FP8><<<grid, kThreads, 0, s>>>(SX, B, d, m, pl.kc, key, part);
+  gsx_lowp_kernel<NB, FP8><<<grid, kThreads, 0, s>>>(SX, B, d, m, pl.kc, key, bscale, part);
 }
 
 }  // namespace
@@ -739,6 +811,9 @@ GsxPlan plan_gsx(int64_t m, int64_t B, int64_t d, Prec prec, int kc_request, siz
     if (kc < 64) kc = 64;
     if (kc > 8192) kc = 8192;
   }
+  // at most 2^23 workgroups along B (a grid holds fewer than 2^32 work-items)
+  const int64_t kc_min = (B + (int64_t)kWaves * (1 << 23) - 1) / ((int64_t)kWaves * (1 << 23));
+  if (kc < kc_min) kc = kc_min;
   kc = (kc + gran - 1) / gran * gran;
   if (kc < gran) kc = gran;
   pl.kc = (int)kc;
@@ -746,9 +821,11 @@ GsxPlan plan_gsx(int64_t m, int64_t B, int64_t d, Prec prec, int kc_request, siz
   return pl;
 }
 
+size_t fp8_scale_bytes(int64_t B) { return align256((size_t)((B + 127) / 128) * sizeof(float2)); }
+
 template <typename T>
 hipError_t launch_gsx_partials(const GsxPlan& pl, Prec prec, const T* SX, int64_t B, int d, int m,
-                               Key key, T* part, hipStream_t s) {
+                               Key key, T* part, hipStream_t s, void* scales, bool scales_ready) {
   if constexpr (sizeof(T) == 8) {
     if (pl.nb == 1)
       launch_native<T, 1>(pl, SX, B, d, m, key, part, s);
@@ -764,17 +841,17 @@ hipError_t launch_gsx_partials(const GsxPlan& pl, Prec prec, const T* SX, int64_
       }
     } else if (prec == Prec::BF16) {
       switch (pl.nb) {
-        case 1: launch_lowp<1, false>(pl, SX, B, d, m, key, part, s); break;
-        case 2: launch_lowp<2, false>(pl, SX, B, d, m, key, part, s); break;
-        case 3: launch_lowp<3, false>(pl, SX, B, d, m, key, part, s); break;
-        default: launch_lowp<4, false>(pl, SX, B, d, m, key, part, s); break;
+        case 1: launch_lowp<1, false>(pl, SX, B, d, m, key, nullptr, part, s); break;
+        case 2: launch_lowp<2, false>(pl, SX, B, d, m, key, nullptr, part, s); break;
+        case 3: launch_lowp<3, false>(pl, SX, B, d, m, key, nullptr, part, s); break;
+        default: launch_lowp<4, false>(pl, SX, B, d, m, key, nullptr, part, s); break;
       }
     } else {
       switch (pl.nb) {
-        case 1: launch_lowp<1, true>(pl, SX, B, d, m, key, part, s); break;
-        case 2: launch_lowp<2, true>(pl, SX, B, d, m, key, part, s); break;
-        case 3: launch_lowp<3, true>(pl, SX, B, d, m, key, part, s); break;
-        default: launch_lowp<4, true>(pl, SX, B, d, m, key, part, s); break;
+        case 1: launch_lowp<1, true>(pl, SX, B, d, m, key, (float2*)scales, part, s, scales_ready); break;
+        case 2: launch_lowp<2, true>(pl, SX, B, d, m, key, (float2*)scales, part, s, scales_ready); break;
+        case 3: launch_lowp<3, true>(pl, SX, B, d, m, key, (float2*)scales, part, s, scales_ready); break;
+        default: launch_lowp<4, true>(pl, SX, B, d, m, key, (float2*)scales, part, s, scales_ready); break;
       }
     }
   }
@@ -787,21 +864,56 @@ hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, 
   return hipGetLastError();
 }
 
-hipError_t launch_rows_partials(const GsxArgs& a0, hipStream_t s) {
+template <int TAG>
+static void launch_rows(const GsxArgs& a, int nb, dim3 grid, hipStream_t s) {
+  switch (nb) {
+    case 1: gx_rows_kernel<1, TAG><<<grid, kThreads, 0, s>>>(a); break;
+    case 2: gx_rows_kernel<2, TAG><<<grid, kThreads, 0, s>>>(a); break;
+    case 3: gx_rows_kernel<3, TAG><<<grid, kThreads, 0, s>>>(a); break;
+    default: gx_rows_kernel<4, TAG><<<grid, kThreads, 0, s>>>(a); break;
+  }
+}
+
+hipError_t launch_rows_partials(const GsxArgs& a0, hipStream_t s, bool dense_gaussian) {
   GsxArgs a = a0;
   a.kc = rows_per_wave(a.n);
   const int64_t parts = rows_parts(a.n, a.kc);
   const int nb = a.d >= 64 ? 4 : (a.d + 15) / 16;
   const int mgroups = (a.m + 63) / 64, ngroups = (a.d + 16 * nb - 1) / (16 * nb);
   dim3 grid((unsigned)parts, (unsigned)mgroups, (unsigned)ngroups);
-  switch (nb) {
-    case 1: gx_rows_kernel<1><<<grid, kThreads, 0, s>>>(a); break;
-    case 2: gx_rows_kernel<2><<<grid, kThreads, 0, s>>>(a); break;
-    case 3: gx_rows_kernel<3><<<grid, kThreads, 0, s>>>(a); break;
-    default: gx_rows_kernel<4><<<grid, kThreads, 0, s>>>(a); break;
+  if (dense_gaussian)
+    launch_rows<2>(a, nb, grid, s);
+  else
+    launch_rows<1>(a, nb, grid, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dense_gaussian_partials(const GsxPlan& pl, const T* X, int64_t ldx, int64_t n,
+                                          int d, int m, Key key, uint64_t row_offset, T* part,
+                                          hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    if (pl.nb == 1)
+      launch_native<T, 1, 2>(pl, X, n, d, m, key, part, s, ldx, row_offset);
+    else
+      launch_native<T, 2, 2>(pl, X, n, d, m, key, part, s, ldx, row_offset);
+  } else {
+    switch (pl.nb) {
+      case 1: launch_native<T, 1, 2>(pl, X, n, d, m, key, part, s, ldx, row_offset); break;
+      case 2: launch_native<T, 2, 2>(pl, X, n, d, m, key, part, s, ldx, row_offset); break;
+      case 3: launch_native<T, 3, 2>(pl, X, n, d, m, key, part, s, ldx, row_offset); break;
+      default: launch_native<T, 4, 2>(pl, X, n, d, m, key, part, s, ldx, row_offset); break;
+    }
   }
   return hipGetLastError();
 }
+
+template hipError_t launch_dense_gaussian_partials<float>(const GsxPlan&, const float*, int64_t,
+                                                          int64_t, int, int, Key, uint64_t, float*,
+                                                          hipStream_t);
+template hipError_t launch_dense_gaussian_partials<double>(const GsxPlan&, const double*, int64_t,
+                                                           int64_t, int, int, Key, uint64_t,
+                                                           double*, hipStream_t);
 
 hipError_t launch_gsx_batched(const GsxArgs* args, const int32_t* gsx_inst,
                               const int32_t* gsx_first, const int64_t items_by_nb[4],
@@ -832,9 +944,9 @@ hipError_t launch_splitk_batched(const GsxArgs* args, const int32_t* red_inst,
 }
 
 template hipError_t launch_gsx_partials<float>(const GsxPlan&, Prec, const float*, int64_t, int,
-                                               int, Key, float*, hipStream_t);
+                                               int, Key, float*, hipStream_t, void*, bool);
 template hipError_t launch_gsx_partials<double>(const GsxPlan&, Prec, const double*, int64_t, int,
-                                                int, Key, double*, hipStream_t);
+                                                int, Key, double*, hipStream_t, void*, bool);
 template hipError_t launch_splitk_reduce<float>(const float*, int64_t, int64_t, float*,
                                                 hipStream_t);
 template hipError_t launch_splitk_reduce<double>(const double*, int64_t, int64_t, double*,

@@ -73,6 +73,9 @@ constexpr int64_t kBinTileRows = 16384;   // default rows per tile (a multiple o
 // kBinTileRows); otherwise a multiple of 1024.
 BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B, int64_t tile_rows = 0);
 size_t binned_scratch_bytes(const BinGeom& g, int64_t count);
+// Whether the binned reduce can write the FP8 block scales (ranges of at
+// least 128 buckets).
+bool binned_emits_fp8_scales(bool csr, int64_t n, int d, int64_t B);
 
 // Everything one binned S X needs (one instance).  The scratch arrays are
 // laid out by bin_carve.
@@ -97,6 +100,13 @@ struct BinArgs {
   uint32_t* hmax;   // R x ntiles: largest |value| bits (CSR)
   uint2* items;     // one per stored entry (CSR) or row (dense)
   float* SX;        // B x d
+  // fused single pass (launch_sx_fused_csr): rows of G and the per-range
+  // partial products (R x m x d)
+  int32_t m;
+  float* part;
+  // if not NULL, the reduce also writes the FP8 contraction's scale pair of
+  // every 128-bucket block (needs 2^bp_shift >= 128)
+  float2* fp8_scale;
 };
 
 // Binned scratch at base: hist | tot | hmax | items (each 256-byte aligned).
@@ -114,13 +124,25 @@ __host__ __device__ inline size_t bin_carve(char* base, int R, int64_t ntiles, i
 
 // `events`, if non-NULL, is the caller's stage-event array; events[1] is
 // recorded after the split plan (counts and scan).
+// fp8_scale: see BinArgs (NULL: not written).
 hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
                                 int64_t n, int64_t nnz, int d, uint32_t B, Key key,
                                 uint64_t row_offset, float* SX, void* scratch, hipStream_t s,
-                                void* const* events);
+                                void* const* events, float2* fp8_scale = nullptr);
 hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d, uint32_t B,
                                   Key key, uint64_t row_offset, float* SX, void* scratch,
-                                  hipStream_t s, void* const* events);
+                                  hipStream_t s, void* const* events, float2* fp8_scale = nullptr);
+
+// The fused single pass for CSR X: the binned split, then one workgroup per
+// bucket range that sums the range's S X slice in LDS and multiplies it by
+// G's columns of those buckets at once, writing part[p] (m x d) for range p
+// of the R = bin_geometry(true, n, d, B).R ranges; S X is never written.
+// Y is then the fixed-order sum of the R partials.  events[1] / [2] are
+// recorded after the split plan and after the scatter.
+hipError_t launch_sx_fused_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
+                               int64_t n, int64_t nnz, int d, uint32_t B, Key key,
+                               uint64_t row_offset, int m, float* part, void* scratch,
+                               hipStream_t s, void* const* events);
 
 // Binned CSR S X of many instances at once: one launch per phase over every
 // instance's work items.  args[i] is instance i (device array); tile_inst /
@@ -146,10 +168,15 @@ struct GsxPlan {
 
 GsxPlan plan_gsx(int64_t m, int64_t B, int64_t d, Prec prec, int kc_request, size_t elem);
 
-// Partial products part[p] (m x d) of workgroup p along B ...
+// Partial products part[p] (m x d) of workgroup p along B ...  FP8 needs
+// `scales`: fp8_scale_bytes(B) of workspace for the per-128-block scales.
+// scales_ready: the S X producer already wrote them (else a scale kernel
+// runs first).
+size_t fp8_scale_bytes(int64_t B);
 template <typename T>
 hipError_t launch_gsx_partials(const GsxPlan& plan, Prec prec, const T* SX, int64_t B, int d,
-                               int m, Key key, T* part, hipStream_t s);
+                               int m, Key key, T* part, hipStream_t s, void* scales = nullptr,
+                               bool scales_ready = false);
 // ... and Y = sum over p of part[p] in increasing p.
 template <typename T>
 hipError_t launch_splitk_reduce(const T* part, int64_t parts, int64_t md, T* Y, hipStream_t s);
@@ -216,7 +243,19 @@ struct GsxArgs {
 // Partial products of the rows route, one per workgroup of the split
 // (grid rows_parts(n, rows_per_wave(n)) x mgroups x ngroups; a.part
 // receives them; a.kc is ignored).
-hipError_t launch_rows_partials(const GsxArgs& a, hipStream_t s);
+// dense_gaussian: the same row-by-row product with the dense Gaussian G~
+// (column row_offset + r for row r, no sign) in place of sigma(r) G[:, h(r)]:
+// G~ X, the product T X stands in for (a.B and the hash are then unused).
+hipError_t launch_rows_partials(const GsxArgs& a, hipStream_t s, bool dense_gaussian = false);
+
+// Partial products of G~ X for dense X (n x d, row stride ldx): the
+// contraction of launch_gsx_partials over the n rows of X, with column
+// row_offset + r of G~ generated in registers for row r.  pl from
+// plan_gsx(m, n, d, Prec::Native, kc, elem).
+template <typename T>
+hipError_t launch_dense_gaussian_partials(const GsxPlan& pl, const T* X, int64_t ldx, int64_t n,
+                                          int d, int m, Key key, uint64_t row_offset, T* part,
+                                          hipStream_t s);
 // 16-column blocks per contraction wavefront of a batched instance: as few
 // as its d needs (one column group below d = 64), else four.  The batch's
 // contraction queue holds the items of each width together, in increasing
@@ -241,6 +280,30 @@ template <typename T>
 hipError_t launch_gather_csr(const int32_t* row_ptr, const int32_t* col_idx, const T* Z,
                              int64_t n, int64_t nnz, int d, uint32_t B, Key key,
                              uint64_t row_offset, T* dvals, hipStream_t s);
+
+// ---- Algorithm 1 (anchor extraction) -----------------------------------
+// imax[i] / imin[i]: the lowest column of the largest / smallest value of
+// row i of Z (m x d, row stride ldz); NaNs never win, -1 for a row of NaNs.
+template <typename T>
+hipError_t launch_row_extrema(const T* Z, int64_t m, int64_t d, int64_t ldz, int32_t* imax,
+                              int32_t* imin, hipStream_t s);
+
+// ---- Section 7 diagnostics ---------------------------------------------
+constexpr int kLemmaMaxD = 64;        // widest U
+constexpr int kLemmaGramRows = 4096;  // rows per Gram partial
+constexpr int kLemmaStats = 6;
+size_t lemma_workspace_bytes(int64_t m, int64_t B, int64_t d, bool with_su);
+// Y: m x d, SU: B x d (or NULL), both row-major with stride d; ws of
+// lemma_workspace_bytes; stats: device double[kLemmaStats].
+template <typename T>
+hipError_t launch_lemma_stats(const T* Y, const T* SU, int64_t m, int64_t B, int d, double* ws,
+                              double* stats, hipStream_t s);
+
+// ---- memory ceilings ----------------------------------------------------
+// kind 0: copy src -> dst; 1: read src (dst receives stream_blocks() words);
+// 2: write dst.  bytes: a multiple of 16, both pointers 16-byte aligned.
+int stream_blocks();
+hipError_t launch_stream(int kind, const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 // ---- test access ------------------------------------------------------
 hipError_t launch_debug_philox(Key key, const uint32_t* ctr, int64_t count, uint32_t* out,

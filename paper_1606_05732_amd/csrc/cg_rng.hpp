@@ -98,6 +98,14 @@ __device__ __forceinline__ Words4 gauss_block(uint32_t b, uint32_t q, uint32_t k
   return philox10(Words4{b, q, 1u, 0u}, k0, k1);
 }
 
+// Words of the dense Gaussian G~ (m x n, the product T X stands in for)
+// column r -- a global row index of X -- row quad q (tag 2): counter
+// (lo32(r), q, 2, hi32(r)).
+__device__ __forceinline__ Words4 dense_gauss_block(uint64_t r, uint32_t q, uint32_t k0,
+                                                    uint32_t k1) {
+  return philox10(Words4{(uint32_t)r, q, 2u, (uint32_t)(r >> 32)}, k0, k1);
+}
+
 __device__ __forceinline__ float unit_f32(uint32_t w) {
   return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
 }

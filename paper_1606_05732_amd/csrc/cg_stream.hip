@@ -1,0 +1,80 @@
+// Streaming probes of the memory system, the ceilings the kernels are
+// measured against: a device copy, a read and a write of `bytes`, with
+// 16-byte accesses, consecutive lanes on consecutive addresses, four
+// accesses in flight per lane, over a grid of several workgroups per CU.
+#include "cg_internal.hpp"
+
+namespace cg {
+
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kThreads = 256;
+constexpr int kUnroll = 4;
+
+__global__ __launch_bounds__(kThreads) void stream_copy_kernel(const u32x4* __restrict__ src,
+                                                               u32x4* __restrict__ dst,
+                                                               int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  for (; i + (kUnroll - 1) * stride < n; i += kUnroll * stride) {
+    u32x4 v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) dst[i + u * stride] = v[u];
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// The xor of everything read, one word per workgroup (so the loads stay).
+__global__ __launch_bounds__(kThreads) void stream_read_kernel(const u32x4* __restrict__ src,
+                                                               uint32_t* __restrict__ out,
+                                                               int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  u32x4 acc = {0u, 0u, 0u, 0u};
+  for (; i + (kUnroll - 1) * stride < n; i += kUnroll * stride) {
+    u32x4 v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) acc ^= v[u];
+  }
+  for (; i < n; i += stride) acc ^= src[i];
+  uint32_t x = acc.x ^ acc.y ^ acc.z ^ acc.w;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x ^= (uint32_t)__shfl_xor((int)x, off, 64);
+  __shared__ uint32_t s[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = 0;
+    for (int w = 0; w < kThreads / 64; ++w) r ^= s[w];
+    out[blockIdx.x] = r;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void stream_write_kernel(u32x4* __restrict__ dst, int64_t n,
+                                                                uint32_t value) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  const u32x4 v = {value, value, value, value};
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) dst[i] = v;
+}
+
+}  // namespace
+
+int stream_blocks() { return 256 * 8; }
+
+hipError_t launch_stream(int kind, const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 16;
+  const unsigned blocks = (unsigned)stream_blocks();
+  switch (kind) {
+    case 0: stream_copy_kernel<<<blocks, kThreads, 0, s>>>((const u32x4*)src, (u32x4*)dst, n); break;
+    case 1: stream_read_kernel<<<blocks, kThreads, 0, s>>>((const u32x4*)src, (uint32_t*)dst, n); break;
+    default: stream_write_kernel<<<blocks, kThreads, 0, s>>>((u32x4*)dst, n, 0x3f800000u); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cg

@@ -32,7 +32,18 @@
 // summed as 64-bit fixed-point integers with ds_add_u64: the range's scale
 // 2^f is chosen from the largest |v| in the range and the item count so
 // that no partial sum can overflow, and integer addition does not depend
-// on order -- the result is bitwise reproducible run to run.  A range that
+// on order -- the result is bitwise reproducible run to run.  Each v 2^f is
+// split into its nearest integer q and a remainder r, |r| <= 1/2.  Most
+// data has r = 0 everywhere (v 2^f is an integer whenever |v| >= 2^(23-f)),
+// and then the q sums are exact; a cell whose q sum is at least 2^24 has
+// lost at most 1/2 per remainder, relatively no more than an FP32 sum of
+// its values would.  Only a range with a cell that received a nonzero
+// remainder and whose |q sum| is below 2^24 (a cell of values far below
+// the range's largest: another column, another bucket) is read a second
+// time, summing the remainders at the finer scale 2^(f + 62 - lg)
+// (lg = ceil(log2 count)) into the same LDS while each thread holds its
+// cells' q sums in registers, so every cell keeps FP32 precision for values
+// down to about max|v| 2^-(100 - 2 lg).  A range that
 // holds a NaN or infinity is summed with float atomics instead (same
 // propagation as the atomic path).
 //
@@ -74,6 +85,8 @@ constexpr size_t kScatterLdsDense = 26 * 1024;
 constexpr int kMinStage = 1024;                // smallest output stage (items)
 constexpr int kSparseRound = 512;              // CSR rounds with at most this many entries skip the stage
 constexpr int kDenseCap = 8192;                // items sorted per dense reduce pass
+constexpr int kCsrMaxCells = 8192;             // cells of a CSR range's S X slice (64 KB of int64)
+constexpr int kDenseMaxBlocks = 128;           // 128-bucket blocks of a dense range (16384 / 128)
 
 static_assert(kTileRows % kRoundRows == 0, "tiles hold whole rounds");
 static_assert(kEPT % 4 == 0, "an entry-parallel chunk is whole 16-byte groups per thread");
@@ -932,7 +945,77 @@ __device__ __forceinline__ void range_of(const uint32_t* __restrict__ tot, int p
   *end = (uint32_t)min(max(e, (uint64_t)*start), (uint64_t)total);
 }
 
-__device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p) {
+// Most cells of one CSR range per thread (cells taken thread-strided).
+constexpr int kCsrCellsPerThread = kCsrMaxCells / kThreads;
+static_assert(kCsrMaxCells % kThreads == 0, "whole cells per thread");
+
+// Calls op(item) for every item [start, end) of a range: two at a time
+// (16-byte loads from an even index; the item buffer is 256-byte aligned),
+// an odd first / last item on its own.
+template <typename Op>
+__device__ __forceinline__ void for_range_items(const uint2* __restrict__ items, uint32_t start,
+                                                uint32_t end, Op&& op) {
+  const uint32_t e0 = min((start + 1) & ~1u, end), e1 = max(end & ~1u, e0);
+  if (threadIdx.x == 0 && start < e0) op(items[start]);
+  if (threadIdx.x == 0 && e1 < end) op(items[e1]);
+  const uint4* __restrict__ pairs = (const uint4*)(items + e0);
+  const uint32_t np = (e1 - e0) / 2;
+  constexpr int UR = 4;
+  uint32_t i = threadIdx.x;
+  for (; i + (UR - 1) * kThreads < np; i += UR * kThreads) {
+    uint4 q[UR];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) q[u] = pairs[i + u * kThreads];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      op(make_uint2(q[u].x, q[u].y));
+      op(make_uint2(q[u].z, q[u].w));
+    }
+  }
+  for (; i < np; i += kThreads) {
+    const uint4 q = pairs[i];
+    op(make_uint2(q.x, q.y));
+    op(make_uint2(q.z, q.w));
+  }
+}
+
+// FP8 scales of the contraction from a range's finished S X slice: one pair
+// (2^-e, 2^(e - 6)) per 128-bucket block, e the smallest integer with
+// amax <= 448 2^e (at least -100), the same rule as the contraction's own
+// scale kernel.  Ranges hold whole blocks (2^bp_shift >= 128 buckets, which
+// bin_geometry gives whenever d <= 64); `value(c)` is cell c's FP32 value.
+template <typename F>
+__device__ __forceinline__ void emit_fp8_scales(const BinArgs& a, int p, int cells, F&& value,
+                                                uint32_t* s_amax) {
+  const int d = a.d, nblk = (1 << a.bp_shift) / 128;
+  for (int i = threadIdx.x; i < nblk; i += kThreads) s_amax[i] = 0u;
+  __syncthreads();
+  for (int c = threadIdx.x; c < cells; c += kThreads) {
+    const float v = fabsf(value(c));
+    if (v == v) atomicMax(&s_amax[(c / d) >> 7], __float_as_uint(v));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nblk; i += kThreads) {
+    const int64_t blk = (((int64_t)p << a.bp_shift) >> 7) + i;
+    if (blk * 128 < (int64_t)a.B) {
+      const float amax = __uint_as_float(s_amax[i]);
+      int e = 0;
+      if (amax > 0.0f) {
+        int E;
+        const float f = frexpf(amax, &E);
+        e = f <= 0.875f ? E - 9 : E - 8;   // 448 = 0.875 * 2^9
+      }
+      e = max(e, -100);
+      a.fp8_scale[blk] = make_float2(ldexpf(1.0f, -e), ldexpf(1.0f, e - 6));
+    }
+  }
+}
+
+// FUSED: the range's S X slice goes to `slice` in LDS (float, cells
+// thread-strided as in s_acc, zero past B) instead of to a.SX, for the
+// fused contraction that follows.
+template <bool FUSED = false>
+__device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p, float* slice = nullptr) {
   const uint2* __restrict__ items = a.items;
   const uint32_t* __restrict__ tot = a.tot;
   const uint32_t* __restrict__ hmax = a.hmax;
@@ -943,8 +1026,12 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p) {
   unsigned long long* s_acc = (unsigned long long*)dyn_lds;
   __shared__ uint32_t s_red[kWaves];
   __shared__ uint64_t s_red64[kWaves];
+  __shared__ int s_resid;
+  __shared__ uint32_t s_rbits[kCsrMaxCells / 32];   // cells that received a nonzero remainder
   const int cells = (1 << bp_shift) * d;
   for (int i = threadIdx.x; i < cells; i += kThreads) s_acc[i] = 0ull;
+  for (int i = threadIdx.x; i < kCsrMaxCells / 32; i += kThreads) s_rbits[i] = 0u;
+  if (threadIdx.x == 0) s_resid = 0;
   uint32_t amax_bits, start, end;   // (the prologue's barrier also orders the zero fill)
   csr_range_prologue(tot, hmax + (int64_t)p * ntiles, ntiles, p, total, s_red, s_red64, &amax_bits,
                      &start, &end);
@@ -960,55 +1047,214 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p) {
     __syncthreads();
     for (int i = threadIdx.x; i < cells; i += kThreads) {
       const int64_t bucket = ((int64_t)p << bp_shift) + i / d;
-      if (bucket < B) SX[bucket * d + i % d] = acc[i];
+      if constexpr (FUSED)
+        slice[i] = bucket < B ? acc[i] : 0.0f;
+      else if (bucket < B)
+        SX[bucket * d + i % d] = acc[i];
+    }
+    if constexpr (!FUSED) {
+      if (a.fp8_scale)
+        emit_fp8_scales(a, p, cells, [&](int c) {
+          const int64_t bucket = ((int64_t)p << bp_shift) + c / d;
+          return bucket < B ? acc[c] : 0.0f;
+        }, s_rbits);
     }
     return;
   }
-  // |partial sums| <= count * amax < 2^(E + lg) with amax < 2^E, count <= 2^lg
+  // |partial q sums| <= count (amax 2^f + 1/2) < 2^62 with amax < 2^E,
+  // count <= 2^lg; |partial remainder sums| <= count 2^(g - 1) <= 2^61
   int E = 0;
   if (amax_bits) frexpf(__uint_as_float(amax_bits), &E);
   const uint32_t count = end - start;
   int lg = 0;
   while (lg < 32 && (1u << lg) < count) ++lg;
-  const int f = 61 - E - lg;
+  const int f = 61 - E - lg, g = 62 - lg;
   const double scale = ldexp(1.0, f), inv = ldexp(1.0, -f);
-  auto add = [&](uint2 it) {
-    if (it.x < (uint32_t)cells)
-      atomicAdd(&s_acc[it.x], (unsigned long long)__double2ll_rn((double)__uint_as_float(it.y) * scale));
-  };
-  // items two at a time (16-byte loads from an even index; the item buffer
-  // is 256-byte aligned), an odd first / last item on its own
-  const uint32_t e0 = min((start + 1) & ~1u, end), e1 = max(end & ~1u, e0);
-  if (threadIdx.x == 0 && start < e0) add(items[start]);
-  if (threadIdx.x == 0 && e1 < end) add(items[e1]);
-  const uint4* __restrict__ pairs = (const uint4*)(items + e0);
-  const uint32_t np = (e1 - e0) / 2;
-  constexpr int UR = 4;
-  uint32_t i = threadIdx.x;
-  for (; i + (UR - 1) * kThreads < np; i += UR * kThreads) {
-    uint4 q[UR];
-#pragma unroll
-    for (int u = 0; u < UR; ++u) q[u] = pairs[i + u * kThreads];
-#pragma unroll
-    for (int u = 0; u < UR; ++u) {
-      add(make_uint2(q[u].x, q[u].y));
-      add(make_uint2(q[u].z, q[u].w));
+  // v 2^f is exact (a power-of-two scale of a float), and so is its
+  // remainder after rounding to the nearest integer
+  for_range_items(items, start, end, [&](uint2 it) {
+    if (it.x < (uint32_t)cells) {
+      const double x = (double)__uint_as_float(it.y) * scale;
+      const double q = rint(x);
+      atomicAdd(&s_acc[it.x], (unsigned long long)(long long)q);
+      if (x != q) atomicOr(&s_rbits[it.x >> 5], 1u << (it.x & 31));
     }
+  });
+  __syncthreads();
+  bool small = false;
+  for (int c = threadIdx.x; c < cells; c += kThreads) {
+    const long long h = (long long)s_acc[c];
+    small |= ((s_rbits[c >> 5] >> (c & 31)) & 1u) && h < (1ll << 24) && h > -(1ll << 24);
   }
-  for (; i < np; i += kThreads) {
-    const uint4 q = pairs[i];
-    add(make_uint2(q.x, q.y));
-    add(make_uint2(q.z, q.w));
+  if (small) s_resid = 1;
+  __syncthreads();
+  if (!s_resid) {
+    for (int c = threadIdx.x; c < cells; c += kThreads) {
+      const int64_t bucket = ((int64_t)p << bp_shift) + c / d;
+      const float v = (float)((double)(long long)s_acc[c] * inv);
+      if constexpr (FUSED)
+        slice[c] = bucket < B ? v : 0.0f;
+      else if (bucket < B)
+        SX[bucket * d + c % d] = v;
+    }
+    if constexpr (!FUSED) {
+      if (a.fp8_scale)
+        emit_fp8_scales(a, p, cells, [&](int c) {
+          const int64_t bucket = ((int64_t)p << bp_shift) + c / d;
+          return bucket < B ? (float)((double)(long long)s_acc[c] * inv) : 0.0f;
+        }, s_rbits);
+    }
+    return;
+  }
+  // second pass: this thread's cells' q sums to registers, then the
+  // remainders summed at scale 2^(f + g) in the same LDS
+  long long hold[kCsrCellsPerThread];
+#pragma unroll
+  for (int k = 0; k < kCsrCellsPerThread; ++k) {
+    const int c = threadIdx.x + k * kThreads;
+    hold[k] = c < cells ? (long long)s_acc[c] : 0ll;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < cells; c += kThreads) {
+  for (int c = threadIdx.x; c < cells; c += kThreads) s_acc[c] = 0ull;
+  __syncthreads();
+  const double rscale = ldexp(1.0, g), rinv = ldexp(1.0, -f - g);
+  for_range_items(items, start, end, [&](uint2 it) {
+    if (it.x < (uint32_t)cells) {
+      const double x = (double)__uint_as_float(it.y) * scale;
+      const double r = x - rint(x);
+      if (r != 0.0) atomicAdd(&s_acc[it.x], (unsigned long long)__double2ll_rn(r * rscale));
+    }
+  });
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kCsrCellsPerThread; ++k) {
+    const int c = threadIdx.x + k * kThreads;
+    if (c >= cells) break;
     const int64_t bucket = ((int64_t)p << bp_shift) + c / d;
-    if (bucket < B) SX[bucket * d + c % d] = (float)((double)(long long)s_acc[c] * inv);
+    const float v = (float)((double)hold[k] * inv + (double)(long long)s_acc[c] * rinv);
+    if constexpr (FUSED)
+      slice[c] = bucket < B ? v : 0.0f;
+    else if (bucket < B)
+      SX[bucket * d + c % d] = v;
+  }
+  if constexpr (!FUSED) {
+    if (a.fp8_scale) {
+      // the range's values were written by this workgroup: read them back
+      __syncthreads();
+      __threadfence_block();
+      emit_fp8_scales(a, p, cells, [&](int c) {
+        const int64_t bucket = ((int64_t)p << bp_shift) + c / d;
+        return bucket < B ? SX[bucket * d + c % d] : 0.0f;
+      }, s_rbits);
+    }
+  }
+}
+
+// ------------------------------------------------------- fused contraction
+// The fused single pass: a range's S X slice, summed in LDS as above, is
+// multiplied at once by the columns of G of the range's buckets (generated
+// in registers), so S X never reaches memory; each range leaves one partial
+// m x d product, and the split reduction adds the R partials in range
+// order (bitwise reproducible).  Four wavefronts take a quarter of the
+// range's buckets each, in steps of four on 16x16x4 FP32 MFMA with the
+// contraction kernel's register tiling (lane (p, kq): G rows 4 q + t of
+// quad q = 16 group + p, K slot kq); for every 64-row group of G and
+// 16 NB-column group of S X in turn, waves 1 .. 3 hand their accumulators
+// to wave 0 through LDS, which adds them in order and writes the partial.
+constexpr int kFusedWaves = 4;
+
+template <int NB>
+__device__ __forceinline__ void fused_contract(const BinArgs& a, int p, const float* slice,
+                                               float* red) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int pl = lane & 15, kq = lane >> 4;
+  const int d = a.d, m = a.m;
+  const int Bp = 1 << a.bp_shift;
+  const int64_t bucket0 = (int64_t)p << a.bp_shift;
+  const int kc = ((Bp + kFusedWaves - 1) / kFusedWaves + 3) & ~3;
+  const int kbeg = wave * kc, kend = min(kbeg + kc, Bp);
+  float* __restrict__ out = a.part + (size_t)p * m * d;
+  const int mgroups = (m + 63) / 64, ngroups = (d + 16 * NB - 1) / (16 * NB);
+  for (int g = 0; g < mgroups; ++g) {
+    const uint32_t q = (uint32_t)(16 * g + pl);
+    for (int ng = 0; ng < ngroups; ++ng) {
+      const int n0 = ng * 16 * NB;
+      v4f acc[4][NB];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
+      if (wave < kFusedWaves) {
+        for (int k0 = kbeg; k0 < kend; k0 += 4) {
+          const int bl = k0 + kq;
+          const int64_t bucket = bucket0 + bl;
+          const bool ok = bl < kend && bucket < (int64_t)a.B;
+          float z[4];
+          box_muller(gauss_block((uint32_t)(ok ? bucket : bucket0), q, a.key.k0, a.key.k1), z);
+          float x[NB];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int c = n0 + nb * 16 + pl;
+            x[nb] = ok && c < d ? slice[bl * d + c] : 0.0f;
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const float gt = ok ? z[t] : 0.0f;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+              acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gt, x[nb], acc[t][nb], 0, 0, 0);
+          }
+        }
+      }
+      constexpr int kVals = 16 * NB;   // accumulator values per lane
+      if (wave > 0 && wave < kFusedWaves) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              red[((wave - 1) * kVals + (t * NB + nb) * 4 + r) * 64 + lane] = acc[t][nb][r];
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int idx = (t * NB + nb) * 4 + r;
+              float sum = acc[t][nb][r];
+#pragma unroll
+              for (int w = 0; w < kFusedWaves - 1; ++w) sum += red[(w * kVals + idx) * 64 + lane];
+              const int row = 4 * (16 * g + 4 * kq + r) + t;
+              const int col = n0 + nb * 16 + pl;
+              if (row < m && col < d) out[(size_t)row * d + col] = sum;
+            }
+      }
+      __syncthreads();   // red is reused by the next group
+    }
   }
 }
 
 __global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(BinArgs a) {
   reduce_csr_range(a, blockIdx.x);
+}
+
+// LDS of the fused kernel: the range's fixed-point sums (64 KB, reused for
+// the cross-wave sums of the contraction) | its FP32 slice (32 KB)
+constexpr size_t kFusedLds = (size_t)kCsrMaxCells * 8 + (size_t)kCsrMaxCells * 4;
+static_assert((size_t)(kFusedWaves - 1) * 16 * 4 * 64 * 4 <= (size_t)kCsrMaxCells * 8,
+              "the cross-wave sums fit in the fixed-point area");
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void bin_reduce_fused_kernel(BinArgs a) {
+  float* slice = (float*)(dyn_lds + (size_t)kCsrMaxCells * 8);
+  reduce_csr_range<true>(a, blockIdx.x, slice);
+  __syncthreads();   // the slice is complete; the fixed-point area is free
+  fused_contract<NB>(a, blockIdx.x, slice, (float*)dyn_lds);
 }
 
 // Dense LDS: slice Bp*d floats | rows and their buckets (kDenseCap) |
@@ -1163,6 +1409,13 @@ __device__ __forceinline__ void reduce_dense_range(const BinArgs& a, int p) {
     const int64_t bucket = ((int64_t)p << bp_shift) + q / d;
     if (bucket < B) SX[bucket * d + q % d] = slice[q];
   }
+  if (a.fp8_scale) {
+    __shared__ uint32_t s_amax[kDenseMaxBlocks];
+    emit_fp8_scales(a, p, cells, [&](int q) {
+      const int64_t bucket = ((int64_t)p << bp_shift) + q / d;
+      return bucket < B ? slice[q] : 0.0f;
+    }, s_amax);
+  }
 }
 
 template <int LPR, int VEC>
@@ -1227,7 +1480,7 @@ BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B, int64_t tile_rows) {
   BinGeom g;
   int shift = 0;
   if (csr) {
-    while (shift < 30 && ((int64_t)2 << shift) * d <= 8192) ++shift;   // int64 cells, 64 KB
+    while (shift < 30 && ((int64_t)2 << shift) * d <= kCsrMaxCells) ++shift;   // int64 cells, 64 KB
     g.lds_bytes = (size_t)(1 << shift) * d * 8;
   } else {
     while (shift < 10 && ((int64_t)2 << shift) * d <= 16384) ++shift;  // float cells, 64 KB
@@ -1254,6 +1507,11 @@ BinGeom bin_geometry(bool csr, int64_t n, int d, int64_t B, int64_t tile_rows) {
   return g;
 }
 
+bool binned_emits_fp8_scales(bool csr, int64_t n, int d, int64_t B) {
+  const BinGeom g = bin_geometry(csr, n, d, B);
+  return g.ok && (1 << g.bp_shift) >= 128;
+}
+
 size_t binned_scratch_bytes(const BinGeom& g, int64_t count) {
   return bin_carve(nullptr, g.R, g.ntiles, count, nullptr);
 }
@@ -1278,9 +1536,10 @@ static BinArgs make_args(const BinGeom& g, int64_t n, int d, uint32_t B, Key key
 hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
                                 int64_t n, int64_t nnz, int d, uint32_t B, Key key,
                                 uint64_t row_offset, float* SX, void* scratch, hipStream_t s,
-                                void* const* events) {
+                                void* const* events, float2* fp8_scale) {
   const BinGeom g = bin_geometry(true, n, d, B);
   BinArgs a = make_args(g, n, d, B, key, row_offset, SX, scratch, nnz);
+  a.fp8_scale = (1 << g.bp_shift) >= 128 ? fp8_scale : nullptr;
   a.row_ptr = row_ptr;
   a.col_idx = col_idx;
   a.vals = vals;
@@ -1298,11 +1557,47 @@ hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, 
   return hipGetLastError();
 }
 
+hipError_t launch_sx_fused_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
+                               int64_t n, int64_t nnz, int d, uint32_t B, Key key,
+                               uint64_t row_offset, int m, float* part, void* scratch,
+                               hipStream_t s, void* const* events) {
+  const BinGeom g = bin_geometry(true, n, d, B);
+  BinArgs a = make_args(g, n, d, B, key, row_offset, nullptr, scratch, nnz);
+  a.row_ptr = row_ptr;
+  a.col_idx = col_idx;
+  a.vals = vals;
+  a.nnz = (int32_t)nnz;
+  a.m = m;
+  a.part = part;
+  const size_t sl = scatter_lds_bytes(g.R, true), cl = count_lds_bytes(g.R);
+  const int nb = d >= 64 ? 4 : (d + 15) / 16;
+  hipError_t e;
+  if ((e = allow_lds(bin_count_kernel<true>, cl)) != hipSuccess) return e;
+  if ((e = allow_lds(bin_scatter_csr_kernel, sl)) != hipSuccess) return e;
+  bin_count_kernel<true><<<(unsigned)g.ntiles, kCntThreads, cl, s>>>(a);
+  bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(a);
+  if (events && events[1] && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
+  bin_scatter_csr_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(a);
+  if (events && events[2] && (e = hipEventRecord((hipEvent_t)events[2], s)) != hipSuccess) return e;
+#define CG_FUSED(NBV)                                                                   \
+  if ((e = allow_lds(bin_reduce_fused_kernel<NBV>, kFusedLds)) != hipSuccess) return e; \
+  bin_reduce_fused_kernel<NBV><<<(unsigned)g.R, kThreads, kFusedLds, s>>>(a);
+  switch (nb) {
+    case 1: CG_FUSED(1) break;
+    case 2: CG_FUSED(2) break;
+    case 3: CG_FUSED(3) break;
+    default: CG_FUSED(4) break;
+  }
+#undef CG_FUSED
+  return hipGetLastError();
+}
+
 hipError_t launch_sx_binned_dense(const float* X, int64_t ldx, int64_t n, int d, uint32_t B,
                                   Key key, uint64_t row_offset, float* SX, void* scratch,
-                                  hipStream_t s, void* const* events) {
+                                  hipStream_t s, void* const* events, float2* fp8_scale) {
   const BinGeom g = bin_geometry(false, n, d, B);
   BinArgs a = make_args(g, n, d, B, key, row_offset, SX, scratch, n);
+  a.fp8_scale = (1 << g.bp_shift) >= 128 ? fp8_scale : nullptr;
   a.X = X;
   a.ldx = ldx;
   const size_t sl = scatter_lds_bytes(g.R, false), cl = count_lds_bytes(g.R);

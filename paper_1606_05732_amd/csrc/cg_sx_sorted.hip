@@ -16,6 +16,8 @@
 // scatter in which each item's rank among equal digits of its tile comes
 // from wavefront ballots -- items are visited in index order, so equal
 // keys keep their input order.
+#include <algorithm>
+
 #include "cg_internal.hpp"
 #include "cg_rng.hpp"
 
@@ -28,6 +30,7 @@ constexpr int kWaves = 4;
 constexpr int kTile = 2048;
 constexpr int kScanChunk = 4096;
 constexpr int kSlotBytes = 16384;  // LDS accumulator bytes per wavefront (CSR reduce)
+constexpr int64_t kBucketsPerLaunch = 1 << 24;   // per-bucket reduce launches: 2^30 work-items
 
 template <typename T>
 struct Entry {
@@ -226,17 +229,31 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
   }
 }
 
-// off[b] = first index of bucket b in the sorted keys, off[B] = count.
+// off[b] = first index of bucket b in the sorted keys, off[B] = count: one
+// thread per bucket (grid-stride), each a binary search for the first key
+// at or above b, so the work per thread is O(log count) however many
+// buckets lie between two keys.
 __global__ __launch_bounds__(kThreads) void bucket_offsets_kernel(const uint32_t* __restrict__ keys,
                                                                   int64_t count, uint32_t B,
                                                                   int32_t* __restrict__ off) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i > count) return;
-  // keys are < B whenever the input is well formed; clamp anyway so that a
-  // malformed CSR can never send a store outside off[0 .. B]
-  const int64_t lo = i == 0 ? 0 : min((int64_t)keys[i - 1], (int64_t)B - 1) + 1;
-  const int64_t hi = i == count ? (int64_t)B : min((int64_t)keys[i], (int64_t)B - 1);
-  for (int64_t b = lo; b <= hi; ++b) off[b] = (int32_t)i;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x; b <= (int64_t)B; b += stride) {
+    int64_t lo = 0, hi = count;
+    if (b == (int64_t)B) {
+      lo = count;
+    } else {
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        // keys are < B whenever the input is well formed; clamped anyway
+        // (a malformed CSR), which keeps them sorted
+        if (min((int64_t)keys[mid], (int64_t)B - 1) < b)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+    }
+    off[b] = (int32_t)lo;
+  }
 }
 
 // ---------------------------------------------------------------- reduce
@@ -245,10 +262,10 @@ __global__ __launch_bounds__(kThreads) void reduce_rows_kernel(const T* __restri
                                                                const int32_t* __restrict__ off,
                                                                const uint32_t* __restrict__ rows,
                                                                int32_t count, uint32_t B, int d,
-                                                               T* __restrict__ SX) {
+                                                               T* __restrict__ SX, int64_t b_base) {
   constexpr int RPP = 64 / LPR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t b = b_base + (int64_t)blockIdx.x * kWaves + wave;
   if (b >= B) return;
   const int32_t s = min(max(off[b], 0), count), e = min(max(off[b + 1], s), count);
   const int sub = lane / LPR, c = lane % LPR;
@@ -279,9 +296,10 @@ __global__ __launch_bounds__(kThreads) void reduce_rows_kernel(const T* __restri
 template <typename T>
 __global__ __launch_bounds__(kThreads) void reduce_rows_wide_kernel(
     const T* __restrict__ X, int64_t ldx, const int32_t* __restrict__ off,
-    const uint32_t* __restrict__ rows, int32_t count, uint32_t B, int d, T* __restrict__ SX) {
+    const uint32_t* __restrict__ rows, int32_t count, uint32_t B, int d, T* __restrict__ SX,
+    int64_t b_base) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t b = b_base + (int64_t)blockIdx.x * kWaves + wave;
   if (b >= B) return;
   const int32_t s = min(max(off[b], 0), count), e = min(max(off[b + 1], s), count);
   for (int c = lane; c < d; c += 64) {
@@ -300,10 +318,11 @@ __global__ __launch_bounds__(kThreads) void reduce_entries_kernel(const int32_t*
                                                                   const Entry<T>* __restrict__ pay,
                                                                   int32_t count, uint32_t B, int d,
                                                                   int slots, int stride,
-                                                                  T* __restrict__ SX) {
+                                                                  T* __restrict__ SX,
+                                                                  int64_t b_base) {
   __shared__ T s_acc[kWaves][kSlotBytes / sizeof(T)];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t b = b_base + (int64_t)blockIdx.x * kWaves + wave;
   T* acc = s_acc[wave];
   const bool live = b < B;
   if (live)
@@ -395,8 +414,8 @@ hipError_t radix_sort(Scratch& s, int64_t count, uint32_t B, hipStream_t st) {
     s.pA = s.pB;
     s.pB = tp;
   }
-  bucket_offsets_kernel<<<(unsigned)((count + kThreads) / kThreads), kThreads, 0, st>>>(
-      s.kA, count, B, s.off);
+  bucket_offsets_kernel<<<(unsigned)std::min<int64_t>(((int64_t)B + kThreads) / kThreads, 8192),
+                          kThreads, 0, st>>>(s.kA, count, B, s.off);
   return hipGetLastError();
 }
 
@@ -426,21 +445,26 @@ hipError_t launch_sx_dense_sorted(const T* X, int64_t ldx, int64_t n, int d, uin
       n, B, key, row_offset, s.kA, (uint32_t*)s.pA);
   hipError_t e = radix_sort<uint32_t>(s, n, B, st);
   if (e != hipSuccess) return e;
-  const unsigned g = (unsigned)(((int64_t)B + kWaves - 1) / kWaves);
   const uint32_t* rows = (const uint32_t*)s.pA;
-  if (d <= 8)
-    reduce_rows_kernel<T, 8><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d, SX);
-  else if (d <= 16)
-    reduce_rows_kernel<T, 16><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d,
-                                                          SX);
-  else if (d <= 32)
-    reduce_rows_kernel<T, 32><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d,
-                                                          SX);
-  else if (d <= 64)
-    reduce_rows_kernel<T, 64><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d,
-                                                          SX);
-  else
-    reduce_rows_wide_kernel<T><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d, SX);
+  // one wavefront per bucket, in launches of at most kBucketsPerLaunch
+  // buckets (a grid holds fewer than 2^32 work-items)
+  for (int64_t b0 = 0; b0 < (int64_t)B; b0 += kBucketsPerLaunch) {
+    const unsigned g = (unsigned)((std::min<int64_t>(kBucketsPerLaunch, (int64_t)B - b0) + kWaves - 1) / kWaves);
+    if (d <= 8)
+      reduce_rows_kernel<T, 8><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d, SX, b0);
+    else if (d <= 16)
+      reduce_rows_kernel<T, 16><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d, SX,
+                                                            b0);
+    else if (d <= 32)
+      reduce_rows_kernel<T, 32><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d, SX,
+                                                            b0);
+    else if (d <= 64)
+      reduce_rows_kernel<T, 64><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d, SX,
+                                                            b0);
+    else
+      reduce_rows_wide_kernel<T><<<g, kThreads, 0, st>>>(X, ldx, s.off, rows, (int32_t)n, B, d,
+                                                           SX, b0);
+  }
   return hipGetLastError();
 }
 
@@ -458,9 +482,11 @@ hipError_t launch_sx_csr_sorted(const int32_t* row_ptr, const int32_t* col_idx, 
   const int stride = d | 1;   // odd row stride: lanes' slot rows fall in different banks
   int slots = (int)(kSlotBytes / sizeof(T)) / stride;
   if (slots > 64) slots = 64;
-  const unsigned g = (unsigned)(((int64_t)B + kWaves - 1) / kWaves);
-  reduce_entries_kernel<T><<<g, kThreads, 0, st>>>(s.off, (const Entry<T>*)s.pA, (int32_t)nnz, B,
-                                                   d, slots, stride, SX);
+  for (int64_t b0 = 0; b0 < (int64_t)B; b0 += kBucketsPerLaunch) {
+    const unsigned g = (unsigned)((std::min<int64_t>(kBucketsPerLaunch, (int64_t)B - b0) + kWaves - 1) / kWaves);
+    reduce_entries_kernel<T><<<g, kThreads, 0, st>>>(s.off, (const Entry<T>*)s.pA, (int32_t)nnz, B,
+                                                     d, slots, stride, SX, b0);
+  }
   return hipGetLastError();
 }
 

@@ -73,8 +73,8 @@ def test_csr_adjoint_parity_and_identity(cuda, dtype):
 def test_finite_differences_on_slice(cuda):
     """X[0:4096, 0:8] of the gradient workload as its own input, m = 128,
     B = 2^19: the GPU adjoint equals the oracle's FP64 adjoint on every
-    entry and central differences (h = 1e-3) of the oracle's forward on a
-    stratified sample of 512 entries (L = <dY, T X> is linear, so the
+    entry, and central differences (h = 1e-3) of the oracle's forward on
+    every one of the 32768 entries (L = <dY, T X> is linear, so the
     differences are exact up to rounding)."""
     n, d, m, B, seed = 4096, 8, 128, 1 << 19, 2004
     rng = np.random.default_rng(1004)
@@ -85,21 +85,25 @@ def test_finite_differences_on_slice(cuda):
     torch.cuda.synchronize()
     dX = dX.cpu().numpy()
     assert rel(dX, O.adjoint_dense(dY, n, d, m, B, seed)) < 1e-12
-    # forward restricted to the buckets the slice touches (G is independent
-    # of X, so this is the same function of X)
+    # the forward restricted to the buckets the slice touches (G is
+    # independent of X, so this is the same function of X): S X by a
+    # scatter of the signed rows, then <dY, G S X> = <G^T dY, S X> with
+    # G^T dY formed once, so that each of the 65536 evaluations costs one
+    # scatter of the perturbed X
     h, sigma = O.hash_rows(seed, B, np.arange(n, dtype=np.uint64))
     used = np.unique(h)
     Gu = np.concatenate([O.gaussian_block(seed, m, int(b), 1) for b in used], axis=1)
-    pos = np.searchsorted(used, h)
+    P = (Gu.T @ dY).ravel()
+    cell = (np.searchsorted(used, h)[:, None] * d + np.arange(d)[None, :]).ravel()
+    sig = np.repeat(sigma.astype(np.float64), d)
 
     def loss(Z):
-        SX = np.zeros((len(used), d))
-        np.add.at(SX, pos, sigma[:, None] * Z)
-        return float(np.sum(dY * (Gu @ SX)))
+        SX = np.bincount(cell, weights=sig * Z.ravel(), minlength=len(used) * d)
+        return float(P @ SX)
 
-    entries = [(int(r), c) for c in range(d) for r in rng.choice(n, 64, replace=False)]
+    entries = [(r, c) for r in range(n) for c in range(d)]
     fd = O.central_fd(loss, X, entries, 1e-3)
-    got = np.array([dX[r, c] for r, c in entries])
+    got = dX.ravel()
     assert np.allclose(got, fd, rtol=1e-7, atol=1e-8)
 
 
@@ -127,6 +131,44 @@ def test_autograd_linear_and_quadratic(cuda):
                                                  seed)[:, 0]
     assert rel(w.grad.cpu().numpy(), g_ref) < 1e-12
     assert abs(loss.item() - float(np.sum(O.sketch_dense(rn, m, B, seed) ** 2))) < 1e-9 * loss.item()
+
+
+def test_autograd_through_csr_values(cuda):
+    """countgauss on a CSR matrix differentiates with respect to its stored
+    values: against the oracle's CSR adjoint (FP64), central differences of
+    the oracle forward over every stored entry, and the quadratic loss
+    ||T X||^2 whose gradient is 2 T^T (T X)."""
+    rng = np.random.default_rng(19)
+    n, d, m, B, seed = 2000, 8, 16, 500, 23
+    rp, ci, v = W.csr_bernoulli(rng, n, d, 0.1, dtype=np.float64)
+    dY = rng.standard_normal((m, d))
+    say("autograd csr", n, d, len(v))
+    vals = torch.from_numpy(v.copy()).to(cuda).requires_grad_(True)
+    X = cg.CsrMatrix(torch.from_numpy(rp).to(cuda), torch.from_numpy(ci).to(cuda), vals, n, d)
+    Y = cg.countgauss(X, m, B, seed)
+    (Y * torch.from_numpy(dY).to(cuda)).sum().backward()
+    torch.cuda.synchronize()
+    g = vals.grad.cpu().numpy()
+    assert rel(g, O.adjoint_csr(rp, ci, dY, n, d, m, B, seed)) < 1e-12
+
+    def loss(V):
+        return float(np.sum(dY * O.sketch_csr(rp, ci, V[:, 0], n, d, m, B, seed)))
+
+    fd = O.central_fd(loss, v[:, None], [(k, 0) for k in range(len(v))], 1e-3)
+    assert np.allclose(g, fd, rtol=1e-7, atol=1e-8)
+    vals.grad = None
+    Y = cg.countgauss(X, m, B, seed)
+    (Y ** 2).sum().backward()
+    torch.cuda.synchronize()
+    y_ref = O.sketch_csr(rp, ci, v, n, d, m, B, seed)
+    assert rel(vals.grad.cpu().numpy(), O.adjoint_csr(rp, ci, 2 * y_ref, n, d, m, B, seed)) < 1e-12
+    # FP32 values through the same path
+    v32 = torch.from_numpy(v.astype(np.float32)).to(cuda).requires_grad_(True)
+    X32 = cg.CsrMatrix(X.row_ptr, X.col_idx, v32, n, d)
+    (cg.countgauss(X32, m, B, seed) * torch.from_numpy(dY.astype(np.float32)).to(cuda)).sum().backward()
+    torch.cuda.synchronize()
+    assert rel(v32.grad.cpu().numpy(), O.adjoint_csr(rp, ci, dY.astype(np.float32).astype(np.float64),
+                                                     n, d, m, B, seed)) < 1e-5
 
 
 def test_workload4_full_size_adjoint(cuda):

@@ -139,7 +139,7 @@ def test_workload5_reduced_scale(cuda):
     say("workload5 x0.02", len(g))
     Ys = cg.sketch_batched(g)
     torch.cuda.synchronize()
-    _check_sample(ws, Ys, range(0, 512, 16))
+    _check_sample(ws, Ys, range(len(ws)))
 
 
 def test_workload5_full_size(cuda):
@@ -149,5 +149,4 @@ def test_workload5_full_size(cuda):
     say("workload5 full", len(g), sum(w.csr.nnz for w in ws))
     Ys = cg.sketch_batched(g)
     torch.cuda.synchronize()
-    big = int(np.argmax([w.csr.nnz for w in ws]))
-    _check_sample(ws, Ys, sorted({0, 1, 100, 255, 400, 511, big}))
+    _check_sample(ws, Ys, range(len(ws)))

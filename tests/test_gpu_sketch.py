@@ -390,3 +390,18 @@ def test_workload2_full_size_dense(cuda):
         y = cg.sketch(Xg, w.m, w.B, w.seed, algo=algo)
         torch.cuda.synchronize()
         assert rel(y.cpu().numpy(), ref) < 1e-5, algo
+
+
+@pytest.mark.parametrize("B", [1 << 24, (1 << 26) + 3])
+def test_sorted_path_with_far_more_buckets_than_entries(cuda, B):
+    """Bucket offsets of the sorted path for B far above the entry count:
+    every empty bucket between two keys still gets its offset (one binary
+    search per bucket)."""
+    n, d, m, seed = 1000, 4, 8, 91
+    rp, ci, v = W.csr_bernoulli(np.random.default_rng(7), n, d, 0.5, dtype=np.float32)
+    say("sorted B >> count", B)
+    X = csr_to_gpu(rp, ci, v, n, d)
+    Y = cg.sketch(X, m, B, seed, algo="sorted")
+    torch.cuda.synchronize()
+    ref = O.sketch_touched(O.csr_to_dense(rp, ci, v, n, d), m, B, seed)
+    assert rel(Y.cpu().numpy(), ref) < 1e-5
