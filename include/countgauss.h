@@ -407,13 +407,16 @@ int cg_get_tuning(int32_t* rows_per_item, int32_t* kc_per_item, int32_t classes)
 /* ---- test access to the random source ---------------------------------- */
 
 /* Memory ceilings for the rooflines: a device copy of `bytes` (src to
- * dst), a read of src (dst receives 2048 uint32 checksums), or a write of
- * dst, with 16-byte accesses on consecutive addresses over 2048
+ * dst), a read of src (dst receives 8192 uint32 checksums), or a write of
+ * dst, with 16-byte accesses on consecutive addresses over 8192
  * workgroups.  bytes: a positive multiple of 16; pointers 16-byte aligned
  * device memory.  stream: hipStream_t.                                    */
 #define CG_STREAM_COPY 0
 #define CG_STREAM_READ 1
 #define CG_STREAM_WRITE 2
+#define CG_STREAM_COPY_NT 3    /* the same with non-temporal accesses   */
+#define CG_STREAM_READ_NT 4
+#define CG_STREAM_WRITE_NT 5
 int cg_debug_stream(int kind, const void* src, void* dst, int64_t bytes,
                     void* stream);
 

@@ -725,9 +725,9 @@ int cg_lemma_stats(const void* Y, const void* SU, int dtype, int64_t m, int64_t 
 }
 
 int cg_debug_stream(int kind, const void* src, void* dst, int64_t bytes, void* stream) {
-  if (kind < CG_STREAM_COPY || kind > CG_STREAM_WRITE) return fail(CG_EINVAL, "unknown stream kind %d", kind);
+  if (kind < CG_STREAM_COPY || kind > CG_STREAM_WRITE_NT) return fail(CG_EINVAL, "unknown stream kind %d", kind);
   if (bytes < 16 || bytes % 16) return fail(CG_EINVAL, "bytes = %lld: a positive multiple of 16", (long long)bytes);
-  if ((kind != CG_STREAM_WRITE && !src) || !dst) return fail(CG_EINVAL, "null pointer argument");
+  if ((kind % 3 != CG_STREAM_WRITE && !src) || !dst) return fail(CG_EINVAL, "null pointer argument");
   if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(CG_EINVAL, "pointers must be 16-byte aligned");
   const hipError_t e = cg::launch_stream(kind, src, dst, bytes, (hipStream_t)stream);
   return e == hipSuccess ? CG_OK : hip_fail(e, "stream probe");

@@ -183,6 +183,13 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
   // the last is a harmless reload)
   T xn[KU][NB];
   load_group(kbeg, xn);
+  // full groups: the normals of the first step (later ones are drawn a
+  // step ahead, below)
+  T gn[4];
+  if constexpr (!HALF) {
+    const int64_t b = kbeg + kq;
+    box_muller(k_block<TAG>(b < kend ? b : kend - 1, col0, q, key), gn);
+  }
   for (int64_t kg = kbeg; kg < kend; kg += 4 * KU) {
     T x[KU][NB];
 #pragma unroll
@@ -223,11 +230,16 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
       for (int u = 0; u < KU; ++u) {
         const int64_t b = kg + 4 * u + kq;
         const bool bok = b < kend;
-        const int64_t cb = bok ? b : kend - 1;
+        // this step's normals were drawn during the step before; the next
+        // step's are drawn now, so that their VALU work can overlap this
+        // step's MFMAs
         T g[4];
-        box_muller(k_block<TAG>(cb, col0, q, key), g);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) g[t] = bok ? g[t] : T(0);
+        for (int t = 0; t < 4; ++t) g[t] = bok ? gn[t] : T(0);
+        {
+          const int64_t bn = b + 4;
+          box_muller(k_block<TAG>(bn < kend ? bn : kend - 1, col0, q, key), gn);
+        }
         T xv[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) xv[nb] = bok && col[nb] < d ? x[u][nb] : T(0);
@@ -242,7 +254,7 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
 }
 
 template <typename T, int NB, int TAG>
-__global__ __launch_bounds__(kThreads) void gsx_native_kernel(const T* __restrict__ SX, int64_t ld,
+__global__ __launch_bounds__(kThreads, 4) void gsx_native_kernel(const T* __restrict__ SX, int64_t ld,
                                                               uint64_t col0, int64_t B, int d, int m,
                                                               int kc, Key key,
                                                               T* __restrict__ part) {
@@ -328,13 +340,15 @@ __global__ __launch_bounds__(kThreads) void fp8_block_scale_kernel(const float* 
 }
 
 // Reduced-precision inputs: BF16 (round to nearest even) or FP8 E4M3 with
-// one power-of-two scale per 128-wide block of B for S X (from
-// fp8_block_scale_kernel) and 2^-6 for G; FP32 accumulation.  K = 32 per
-// MFMA: lane (p, kq) supplies the eight columns b = base + 8 kq + e,
-// e = 0..7, i.e. eight Philox blocks per step.  A step's S X values are
-// loaded one step ahead, so their latency hides behind the step before.
+// one power-of-two scale per 128-wide block of B for S X (from the binned
+// S X reduce or fp8_block_scale_kernel) and 2^-6 for G; FP32
+// accumulation.  K = 32 per MFMA: lane (p, kq) supplies the eight columns
+// b = base + 8 kq + e, e = 0..7, i.e. eight Philox blocks per step.  A
+// step's S X values are loaded one step ahead and packed into the MFMA
+// operand format as soon as the step begins, so only one step of FP32
+// values is ever held (registers decide the occupancy here).
 template <int NB, bool FP8>
-__global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restrict__ SX,
+__global__ __launch_bounds__(kThreads, 4) void gsx_lowp_kernel(const float* __restrict__ SX,
                                                             int64_t B, int d, int m, int kc,
                                                             Key key, const float2* __restrict__ bscale,
                                                             float* __restrict__ part) {
@@ -350,17 +364,19 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
-  int col[NB], ccol[NB];
+  int ccol[NB];
+  bool cok[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    col[nb] = n0 + nb * 16 + p;
-    ccol[nb] = min(col[nb], d - 1);
+    const int col = n0 + nb * 16 + p;
+    cok[nb] = col < d;
+    ccol[nb] = min(col, d - 1);
   }
 
   const int64_t kbeg = ((int64_t)blockIdx.x * kWaves + wave) * kc;
   const int64_t kend = min(kbeg + (int64_t)kc, B);
   // this lane's eight S X rows of the step at `base`, clamped (values past
-  // the chunk or the columns are zeroed where they are used)
+  // the chunk or the columns are zeroed when they are packed)
   auto load_step = [&](int64_t base, float (&x)[8][NB]) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -382,45 +398,53 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
     // FP8 block products are rescaled before they join the accumulator;
     // BF16 needs no scale and accumulates directly
     v4f tmp[4][NB];
+    if constexpr (FP8) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) tmp[t][nb] = v4f{0, 0, 0, 0};
+        for (int nb = 0; nb < NB; ++nb) tmp[t][nb] = v4f{0, 0, 0, 0};
+    }
 #pragma unroll
     for (int sub = 0; sub < KBLK / 32; ++sub) {
       const int64_t base = kb + sub * 32 + kq * 8;
-      float x[8][NB];
+      // this step's S X operand, packed from the values that arrived
+      int xlo[NB], xhi[NB];
+      v8bf xb[NB];
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
+      for (int nb = 0; nb < NB; ++nb) {
+        xlo[nb] = xhi[nb] = 0;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) x[e][nb] = xn[e][nb];
+        for (int e = 0; e < 8; e += 2) {
+          const bool ok0 = base + e < kend && cok[nb], ok1 = base + e + 1 < kend && cok[nb];
+          const float x0 = ok0 ? xn[e][nb] : 0.0f, x1 = ok1 ? xn[e + 1][nb] : 0.0f;
+          if constexpr (FP8) {
+            int& w = e < 4 ? xlo[nb] : xhi[nb];
+            w = (e & 2) ? cvt_fp8<true>(x0 * xscale, x1 * xscale, w)
+                        : cvt_fp8<false>(x0 * xscale, x1 * xscale, w);
+          } else {
+            xb[nb][e] = (__bf16)x0;
+            xb[nb][e + 1] = (__bf16)x1;
+          }
+        }
+      }
       // the next step's rows (the step after the last is a harmless reload)
       load_step(base + 32, xn);
-      // operands packed as they are produced, two columns of B at a time;
-      // normals unguarded at clamped indices, values past the chunk or the
-      // columns zeroed
+      // G's operand, two columns of B at a time; normals unguarded at
+      // clamped indices, zeroed past the chunk
       int glo[4] = {0, 0, 0, 0}, ghi[4] = {0, 0, 0, 0};
-      int xlo[NB], xhi[NB];
-      v8bf gb[4], xb[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) xlo[nb] = xhi[nb] = 0;
+      v8bf gb[4];
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
         const int64_t b0 = base + e, b1 = b0 + 1;
         const bool ok0 = b0 < kend, ok1 = b1 < kend;
         const int64_t c0 = ok0 ? b0 : kend - 1, c1 = ok1 ? b1 : kend - 1;
-        float z0[4], z1[4], x0[NB], x1[NB];
+        float z0[4], z1[4];
         box_muller(gauss_block((uint32_t)c0, q, key.k0, key.k1), z0);
         box_muller(gauss_block((uint32_t)c1, q, key.k0, key.k1), z1);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           z0[t] = ok0 ? z0[t] : 0.0f;
           z1[t] = ok1 ? z1[t] : 0.0f;
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          x0[nb] = ok0 && col[nb] < d ? x[e][nb] : 0.0f;
-          x1[nb] = ok1 && col[nb] < d ? x[e + 1][nb] : 0.0f;
         }
         if constexpr (FP8) {
           // columns e, e + 1 go to byte pair (e / 2) % 2 of word e / 4
@@ -430,22 +454,11 @@ __global__ __launch_bounds__(kThreads) void gsx_lowp_kernel(const float* __restr
             w = (e & 2) ? cvt_fp8<true>(z0[t] * 64.0f, z1[t] * 64.0f, w)
                         : cvt_fp8<false>(z0[t] * 64.0f, z1[t] * 64.0f, w);
           }
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            int& w = e < 4 ? xlo[nb] : xhi[nb];
-            w = (e & 2) ? cvt_fp8<true>(x0[nb] * xscale, x1[nb] * xscale, w)
-                        : cvt_fp8<false>(x0[nb] * xscale, x1[nb] * xscale, w);
-          }
         } else {
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             gb[t][e] = (__bf16)z0[t];
             gb[t][e + 1] = (__bf16)z1[t];
-          }
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            xb[nb][e] = (__bf16)x0[nb];
-            xb[nb][e + 1] = (__bf16)x1[nb];
           }
         }
       }

@@ -1,7 +1,8 @@
 // Streaming probes of the memory system, the ceilings the kernels are
-// measured against: a device copy, a read and a write of `bytes`, with
-// 16-byte accesses, consecutive lanes on consecutive addresses, four
-// accesses in flight per lane, over a grid of several workgroups per CU.
+// measured against: a device copy, a read and a write of `bytes` (plain or
+// non-temporal accesses), with
+// 16-byte accesses, consecutive lanes on consecutive addresses, eight
+// accesses in flight per lane, over a grid of 32 workgroups per CU.
 #include "cg_internal.hpp"
 
 namespace cg {
@@ -10,8 +11,23 @@ namespace {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;
 
+// NT: non-temporal accesses (streamed past the caches).
+template <bool NT>
+__device__ __forceinline__ u32x4 ld(const u32x4* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st(u32x4* p, u32x4 v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <bool NT>
 __global__ __launch_bounds__(kThreads) void stream_copy_kernel(const u32x4* __restrict__ src,
                                                                u32x4* __restrict__ dst,
                                                                int64_t n) {
@@ -20,14 +36,15 @@ __global__ __launch_bounds__(kThreads) void stream_copy_kernel(const u32x4* __re
   for (; i + (kUnroll - 1) * stride < n; i += kUnroll * stride) {
     u32x4 v[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) v[u] = src[i + u * stride];
+    for (int u = 0; u < kUnroll; ++u) v[u] = ld<NT>(src + i + u * stride);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) dst[i + u * stride] = v[u];
+    for (int u = 0; u < kUnroll; ++u) st<NT>(dst + i + u * stride, v[u]);
   }
-  for (; i < n; i += stride) dst[i] = src[i];
+  for (; i < n; i += stride) st<NT>(dst + i, ld<NT>(src + i));
 }
 
 // The xor of everything read, one word per workgroup (so the loads stay).
+template <bool NT>
 __global__ __launch_bounds__(kThreads) void stream_read_kernel(const u32x4* __restrict__ src,
                                                                uint32_t* __restrict__ out,
                                                                int64_t n) {
@@ -37,11 +54,11 @@ __global__ __launch_bounds__(kThreads) void stream_read_kernel(const u32x4* __re
   for (; i + (kUnroll - 1) * stride < n; i += kUnroll * stride) {
     u32x4 v[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) v[u] = src[i + u * stride];
+    for (int u = 0; u < kUnroll; ++u) v[u] = ld<NT>(src + i + u * stride);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) acc ^= v[u];
   }
-  for (; i < n; i += stride) acc ^= src[i];
+  for (; i < n; i += stride) acc ^= ld<NT>(src + i);
   uint32_t x = acc.x ^ acc.y ^ acc.z ^ acc.w;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x ^= (uint32_t)__shfl_xor((int)x, off, 64);
@@ -55,24 +72,35 @@ __global__ __launch_bounds__(kThreads) void stream_read_kernel(const u32x4* __re
   }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kThreads) void stream_write_kernel(u32x4* __restrict__ dst, int64_t n,
                                                                 uint32_t value) {
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   const u32x4 v = {value, value, value, value};
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) dst[i] = v;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) st<NT>(dst + i, v);
 }
 
 }  // namespace
 
-int stream_blocks() { return 256 * 8; }
+int stream_blocks() { return 256 * 32; }
 
 hipError_t launch_stream(int kind, const void* src, void* dst, int64_t bytes, hipStream_t s) {
   const int64_t n = bytes / 16;
   const unsigned blocks = (unsigned)stream_blocks();
-  switch (kind) {
-    case 0: stream_copy_kernel<<<blocks, kThreads, 0, s>>>((const u32x4*)src, (u32x4*)dst, n); break;
-    case 1: stream_read_kernel<<<blocks, kThreads, 0, s>>>((const u32x4*)src, (uint32_t*)dst, n); break;
-    default: stream_write_kernel<<<blocks, kThreads, 0, s>>>((u32x4*)dst, n, 0x3f800000u); break;
+  const bool nt = kind >= 3;
+  switch (kind % 3) {
+    case 0:
+      if (nt) stream_copy_kernel<true><<<blocks, kThreads, 0, s>>>((const u32x4*)src, (u32x4*)dst, n);
+      else stream_copy_kernel<false><<<blocks, kThreads, 0, s>>>((const u32x4*)src, (u32x4*)dst, n);
+      break;
+    case 1:
+      if (nt) stream_read_kernel<true><<<blocks, kThreads, 0, s>>>((const u32x4*)src, (uint32_t*)dst, n);
+      else stream_read_kernel<false><<<blocks, kThreads, 0, s>>>((const u32x4*)src, (uint32_t*)dst, n);
+      break;
+    default:
+      if (nt) stream_write_kernel<true><<<blocks, kThreads, 0, s>>>((u32x4*)dst, n, 0x3f800000u);
+      else stream_write_kernel<false><<<blocks, kThreads, 0, s>>>((u32x4*)dst, n, 0x3f800000u);
+      break;
   }
   return hipGetLastError();
 }

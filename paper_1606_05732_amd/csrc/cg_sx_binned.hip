@@ -1072,22 +1072,32 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p, float*
   const double scale = ldexp(1.0, f), inv = ldexp(1.0, -f);
   // v 2^f is exact (a power-of-two scale of a float), and so is its
   // remainder after rounding to the nearest integer
+  bool any_rem = false;
   for_range_items(items, start, end, [&](uint2 it) {
     if (it.x < (uint32_t)cells) {
       const double x = (double)__uint_as_float(it.y) * scale;
       const double q = rint(x);
       atomicAdd(&s_acc[it.x], (unsigned long long)(long long)q);
-      if (x != q) atomicOr(&s_rbits[it.x >> 5], 1u << (it.x & 31));
+      if (x != q) {
+        atomicOr(&s_rbits[it.x >> 5], 1u << (it.x & 31));
+        any_rem = true;
+      }
     }
   });
+  if (any_rem) s_resid = 2;   // some remainder: look at the cells
   __syncthreads();
-  bool small = false;
-  for (int c = threadIdx.x; c < cells; c += kThreads) {
-    const long long h = (long long)s_acc[c];
-    small |= ((s_rbits[c >> 5] >> (c & 31)) & 1u) && h < (1ll << 24) && h > -(1ll << 24);
+  if (s_resid == 2) {
+    __syncthreads();   // every thread has read the flag before it is reset
+    if (threadIdx.x == 0) s_resid = 0;
+    __syncthreads();
+    bool small = false;
+    for (int c = threadIdx.x; c < cells; c += kThreads) {
+      const long long h = (long long)s_acc[c];
+      small |= ((s_rbits[c >> 5] >> (c & 31)) & 1u) && h < (1ll << 24) && h > -(1ll << 24);
+    }
+    if (small) s_resid = 1;
+    __syncthreads();
   }
-  if (small) s_resid = 1;
-  __syncthreads();
   if (!s_resid) {
     for (int c = threadIdx.x; c < cells; c += kThreads) {
       const int64_t bucket = ((int64_t)p << bp_shift) + c / d;
