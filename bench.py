@@ -50,6 +50,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_FP32_TFLOPS = 157.3
+# dense MFMA peaks of MI355X per input type (TFLOP/s), without sparsity
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 METRIC = "T·X nnz/sec and % HBM roofline at 1 GPU; fused BF16/FP8 vs FP32 at stated error"
 COUNTERS = os.path.join(ROOT, "profiles", "sx_stage_csr_n16777216_d32_counters.json")
 SX_SOURCES = [os.path.join(ROOT, "paper_1606_05732_amd", "csrc", f)
@@ -239,6 +241,25 @@ def cpu_baseline_all_cores(w, procs):
                       f"{t:.2f} s"}
 
 
+def normals_ceiling(m, B, seed, reps=20):
+    """The generator's own ceiling: time for the library to draw the m x B
+    normals of G and nothing else (cg_debug_normals, the contractions'
+    counters and FP32 Box-Muller), with events around `reps` launches."""
+    import torch
+
+    from paper_1606_05732_amd import _lib as L
+    lib = L.load()
+    sink = torch.empty(L.CG_NORMALS_SINK, dtype=torch.float32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call():
+        L.check(lib.cg_debug_normals(seed, m, B, ctypes.c_void_p(sink.data_ptr()), stream),
+                "cg_debug_normals")
+    ms = event_time_ms(call, reps, 3)
+    del sink
+    return ms * 1e3
+
+
 def ladder(steps, warmup, ev):
     import numpy as np  # noqa: F401
     import torch
@@ -251,17 +272,29 @@ def ladder(steps, warmup, ev):
     ref = O.sketch_dense(w.dense, w.m, w.B, w.seed)
     X = torch.from_numpy(w.dense).to("cuda")
     out = {"workload": w.name, "nnz": int(w.nnz)}
+    # every rung draws the same m B normals: the generator's ceiling bounds
+    # the contraction from below whatever the MFMA type
+    rng_us = normals_ceiling(w.m, w.B, w.seed)
+    out["rng_bound_us"] = round(rng_us, 2)
+    out["rng_normals_per_s"] = float(f"{w.m * w.B / (rng_us * 1e-6):.4g}")
+    log(f"ladder: drawing the {w.m} x {w.B} normals alone takes {rng_us:.1f} us")
     for prec in ("native", "bf16", "fp8"):
         plan = cg.SketchPlan(X, w.m, w.B, w.seed, precision=prec)
         wall, stage, total, _ = timed_steps(plan, steps, warmup, ev)
         err = O.rel_frobenius(plan.Y.cpu().numpy(), ref)
         flops = 2.0 * w.m * w.B * w.d
-        out["fp32" if prec == "native" else prec] = {
+        rung = "fp32" if prec == "native" else prec
+        tflops = flops / (stage["gsx"] * 1e-3) / 1e12
+        out[rung] = {
             "ms_per_step": round(wall, 4), "gsx_us": round(stage["gsx"] * 1e3, 2),
             "sx_us": round((stage["sx_prologue"] + stage["sx"]) * 1e3, 2),
-            "gsx_tflops": round(flops / (stage["gsx"] * 1e-3) / 1e12, 2),
+            "gsx_tflops": round(tflops, 2),
+            "mfma_peak_tflops": MFMA_PEAK_TFLOPS[rung],
+            "frac_of_mfma_peak": round(tflops / MFMA_PEAK_TFLOPS[rung], 4),
+            "frac_of_rng_bound": round(rng_us / (stage["gsx"] * 1e3), 3),
             "rel_fro_err_vs_fp64": float(f"{err:.3e}")}
-        log(f"ladder {prec}: {wall:.3f} ms/step, gsx {stage['gsx']*1e3:.1f} us, err {err:.2e}")
+        log(f"ladder {prec}: {wall:.3f} ms/step, gsx {stage['gsx']*1e3:.1f} us "
+            f"({rng_us / (stage['gsx'] * 1e3):.2f} of the generator's ceiling), err {err:.2e}")
         del plan
     del X
     torch.cuda.empty_cache()

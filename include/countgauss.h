@@ -420,6 +420,16 @@ int cg_get_tuning(int32_t* rows_per_item, int32_t* kc_per_item, int32_t classes)
 int cg_debug_stream(int kind, const void* src, void* dst, int64_t bytes,
                     void* stream);
 
+/* The generator's ceiling for the contraction rooflines: draws the m x B
+ * normals of G (columns 0 .. B-1, rows 0 .. m-1, the counters and FP32
+ * Box-Muller the contractions use; Section 1.1's G) and nothing else; each
+ * of CG_NORMALS_SINK threads writes the sum of its normals to sink[t].
+ * m: a positive multiple of 4 up to 2^24; 1 <= B < 2^31.  sink: device
+ * float[CG_NORMALS_SINK].  stream: hipStream_t.                           */
+#define CG_NORMALS_SINK (1 << 21)
+int cg_debug_normals(uint64_t seed, int64_t m, int64_t B, float* sink,
+                     void* stream);
+
 /* out[4k..4k+3] = Philox4x32-10(counter ctr[4k..4k+3], key(seed)) for
  * k < count.  ctr, out: device uint32 arrays.  stream: hipStream_t. */
 int cg_debug_philox(uint64_t seed, const uint32_t* ctr, int64_t count,

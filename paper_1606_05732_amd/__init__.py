@@ -7,7 +7,8 @@ include/countgauss.h).  This package is a thin binding: torch provides
 device memory and streams.
 """
 from .api import (anchors, BatchedSketch, CsrMatrix, CountGaussCsrFn, CountGaussFn, countgauss,  # noqa: F401
-                  debug_gaussian, debug_hash, debug_philox, gaussian, get_tuning, lemma_stats, LEMMA_STATS,
+                  debug_gaussian, debug_hash, debug_normals, debug_philox, gaussian, get_tuning,
+                  lemma_stats, LEMMA_STATS,
                   row_extrema, set_tuning, sketch,
                   sketch_adjoint, sketch_adjoint_csr, sketch_batched, sketch_csr_noalloc,
                   SketchPlan)

@@ -19,6 +19,7 @@ CG_PROJ_COUNTGAUSS, CG_PROJ_GAUSSIAN = 0, 1
 CG_KIND_LEMMA = 8
 CG_STREAM_COPY, CG_STREAM_READ, CG_STREAM_WRITE = 0, 1, 2
 CG_STREAM_COPY_NT, CG_STREAM_READ_NT, CG_STREAM_WRITE_NT = 3, 4, 5
+CG_NORMALS_SINK = 1 << 21
 
 # Every function declared in include/countgauss.h.
 EXPORTS = [
@@ -26,7 +27,7 @@ EXPORTS = [
     "cg_workspace_bytes", "cg_sketch_csr", "cg_sketch_dense", "cg_sketch_adjoint",
     "cg_sketch_adjoint_csr", "cg_batched_plan", "cg_sketch_batched", "cg_set_tuning",
     "cg_get_tuning", "cg_sketch_csr_noalloc", "cg_gaussian_dense", "cg_gaussian_csr",
-    "cg_row_extrema", "cg_anchors_dense", "cg_lemma_stats", "cg_debug_stream",
+    "cg_row_extrema", "cg_anchors_dense", "cg_lemma_stats", "cg_debug_stream", "cg_debug_normals",
     "cg_debug_philox", "cg_debug_hash", "cg_debug_gaussian",
 ]
 
@@ -148,6 +149,7 @@ def load():
         "cg_set_tuning": (ctypes.c_int, [ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I32]),
         "cg_get_tuning": (ctypes.c_int, [ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I32]),
         "cg_debug_stream": (ctypes.c_int, [ctypes.c_int, _P, _P, _I64, _P]),
+        "cg_debug_normals": (ctypes.c_int, [_U64, _I64, _I64, _P, _P]),
         "cg_debug_philox": (ctypes.c_int, [_U64, _P, _I64, _P, _P]),
         "cg_debug_hash": (ctypes.c_int, [_U64, _I64, _U64, _I64, _P, _P, _P]),
         "cg_debug_gaussian": (ctypes.c_int, [_U64, _I64, _I64, _I64, ctypes.c_int, _P, _P]),

@@ -405,6 +405,16 @@ def debug_gaussian(seed, m, b0, nb, dtype=torch.float32, device="cuda"):
     return G
 
 
+def debug_normals(seed, m, B, device="cuda"):
+    """Per-thread sums of the m x B normals of G (the generator-only probe
+    behind the contraction rooflines): a float tensor of CG_NORMALS_SINK."""
+    lib = L.load()
+    sink = torch.empty(L.CG_NORMALS_SINK, dtype=torch.float32, device=device)
+    L.check(lib.cg_debug_normals(ctypes.c_uint64(seed & (2 ** 64 - 1)), m, B, _ptr(sink),
+                                 _stream(torch.device(device))), "cg_debug_normals")
+    return sink
+
+
 class SketchPlan:
     """A forward call with every buffer allocated up front: Y, optional S X
     and the workspace.  run() only queues the library's kernels on the

@@ -24,6 +24,11 @@ SOURCES = ["cg_sx_atomic.hip", "cg_sx_sorted.hip", "cg_sx_binned.hip", "cg_gsx.h
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-munsafe-fp-atomics",
+    # MFMA results in ordinary VGPRs: gfx950's register file is unified, and
+    # with accumulators in AGPRs the allocator copies some of them between
+    # register classes on every loop iteration (the FP32 contraction and
+    # G^T dY lose those copies and gain occupancy this way)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     # no packed-FP32 instructions in the device code (the host pass does not
     # know the feature and warns; tests/test_build_no_packed_fp32.py checks
     # the device assembly)

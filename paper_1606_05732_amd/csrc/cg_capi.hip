@@ -733,6 +733,15 @@ int cg_debug_stream(int kind, const void* src, void* dst, int64_t bytes, void* s
   return e == hipSuccess ? CG_OK : hip_fail(e, "stream probe");
 }
 
+int cg_debug_normals(uint64_t seed, int64_t m, int64_t B, float* sink, void* stream) {
+  if (m < 4 || m % 4 || m > (1LL << 24)) return fail(CG_EINVAL, "m = %lld: a positive multiple of 4 up to 2^24", (long long)m);
+  if (B < 1 || B > 0x7fffffffLL) return fail(CG_EINVAL, "B = %lld outside [1, 2^31)", (long long)B);
+  if (!sink) return fail(CG_EINVAL, "null pointer argument");
+  if (cg::normals_threads() != CG_NORMALS_SINK) return fail(CG_EUNSUPPORTED, "sink size mismatch");
+  const hipError_t e = cg::launch_normals_rate(cg::key_of(seed), m, B, sink, (hipStream_t)stream);
+  return e == hipSuccess ? CG_OK : hip_fail(e, "normals probe");
+}
+
 int cg_debug_philox(uint64_t seed, const uint32_t* ctr, int64_t count, uint32_t* out,
                     void* stream) {
   if (count < 0 || count > (1LL << 30)) return fail(CG_EINVAL, "count %lld out of range", (long long)count);

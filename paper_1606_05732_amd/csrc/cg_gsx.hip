@@ -69,7 +69,10 @@ __device__ __forceinline__ int d_row(int kq, int r) {
 
 // Sum the four wavefronts' accumulators (wave 0 + 1 + 2 + 3, in that
 // order) and write the workgroup's partial product rows/cols that exist.
-template <typename T, int NB, typename V>
+// VEC: lane p's NB column blocks hold the consecutive columns
+// n0 + NB p + nb (so that one vector load fetches them) instead of
+// n0 + 16 nb + p.
+template <typename T, int NB, typename V, bool VEC = false>
 __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int wave, int lane,
                                                    int group, int n0, int m, int d,
                                                    T* __restrict__ out) {
@@ -98,7 +101,7 @@ __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int 
         s += red[(1 * R + idx) * 64 + lane];
         s += red[(2 * R + idx) * 64 + lane];
         const int row = 4 * (16 * group + d_row<T>(kq, r)) + t;
-        const int col = n0 + nb * 16 + p;
+        const int col = VEC ? n0 + NB * p + nb : n0 + nb * 16 + p;
         if (row < m && col < d) out[(size_t)row * d + col] = s;
       }
 }
@@ -347,11 +350,67 @@ __global__ __launch_bounds__(kThreads) void fp8_block_scale_kernel(const float* 
 // step's S X values are loaded one step ahead and packed into the MFMA
 // operand format as soon as the step begins, so only one step of FP32
 // values is ever held (registers decide the occupancy here).
-template <int NB, bool FP8>
-__global__ __launch_bounds__(kThreads, 4) void gsx_lowp_kernel(const float* __restrict__ SX,
-                                                            int64_t B, int d, int m, int kc,
-                                                            Key key, const float2* __restrict__ bscale,
+//
+// The kernel is bound by the vector ALUs (Philox's 64-bit products and
+// Box-Muller's transcendentals), so the rest is kept lean:
+//  * VEC (NB = 2 or 4, d a multiple of 16 NB): lane p takes the NB
+//    consecutive columns n0 + NB p + nb, one 8- or 16-byte load per row;
+//  * rows are addressed by 32-bit element offsets from S X (the host
+//    checks B d < 2^31), advanced by a wavefront-uniform step and clamped
+//    to the chunk's last row with one min;
+//  * a 128-column block wholly inside the chunk (all but at most one per
+//    wavefront) takes no per-column masks;
+//  * normals and S X values are converted two at a time.
+// Eight rows from byte offset `off` (row b's first element), `dstep`
+// bytes apart, clamped to `last` (the chunk's last row); the elements at
+// byte offsets `col[nb]` of each (with VEC, from col[0] on).  32-bit byte
+// offsets from a wavefront-uniform base let the loads use the
+// scalar-base addressing form.
+template <int NB, bool VEC>
+__device__ __forceinline__ void lowp_load_rows(const float* __restrict__ SX, uint32_t off,
+                                               uint32_t dstep, uint32_t last,
+                                               const uint32_t (&col)[NB], float (&x)[8][NB]) {
+  const char* base = (const char*)SX;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t o = min(off + (uint32_t)e * dstep, last);
+    if constexpr (VEC && NB == 4) {
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      const f4 v = *(const f4*)(base + (o + col[0]));
+      x[e][0] = v.x;
+      x[e][1] = v.y;
+      x[e][2] = v.z;
+      x[e][3] = v.w;
+    } else if constexpr (VEC && NB == 2) {
+      typedef float f2 __attribute__((ext_vector_type(2)));
+      const f2 v = *(const f2*)(base + (o + col[0]));
+      x[e][0] = v.x;
+      x[e][1] = v.y;
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) x[e][nb] = *(const float*)(base + (o + col[nb]));
+    }
+  }
+}
+
+// Two FP32 values to a BF16 pair (round to nearest even), a in the low half.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  const bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// One launch covers the parts bx0 + blockIdx.x; SX points at row row0 of
+// S X (the host splits the parts so that every row a launch reads lies
+// below row0 + 2^30 / d).
+template <int NB, bool FP8, bool VEC>
+__global__ __launch_bounds__(kThreads, FP8 ? 2 : 4) void gsx_lowp_kernel(const float* __restrict__ SX,
+                                                            int64_t row0, int64_t bx0, int64_t B,
+                                                            int d, int m, int kc, Key key,
+                                                            const float2* __restrict__ bscale,
                                                             float* __restrict__ part) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  // columns per block: one FP8 scale; one decision whether masks are needed
   constexpr int KBLK = FP8 ? 128 : 32;
   __shared__ float red[3 * 16 * NB * 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -364,30 +423,30 @@ __global__ __launch_bounds__(kThreads, 4) void gsx_lowp_kernel(const float* __re
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
-  int ccol[NB];
+  // this lane's columns, each clamped onto d - 1 when past it (such
+  // columns are zeroed when packed; with VEC they do not occur)
   bool cok[NB];
+  uint32_t ccol[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    const int col = n0 + nb * 16 + p;
+    const int col = VEC ? n0 + NB * p + nb : n0 + 16 * nb + p;
     cok[nb] = col < d;
-    ccol[nb] = min(col, d - 1);
+    ccol[nb] = 4u * (uint32_t)min(col, d - 1);   // bytes
   }
 
-  const int64_t kbeg = ((int64_t)blockIdx.x * kWaves + wave) * kc;
+  const int64_t bx = bx0 + blockIdx.x;
+  const int64_t kbeg = (bx * kWaves + wave) * kc;
   const int64_t kend = min(kbeg + (int64_t)kc, B);
-  // this lane's eight S X rows of the step at `base`, clamped (values past
-  // the chunk or the columns are zeroed when they are packed)
-  auto load_step = [&](int64_t base, float (&x)[8][NB]) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t b = base + e;
-      const int64_t c = b < kend ? b : kend - 1;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x[e][nb] = SX[c * d + ccol[nb]];
-    }
-  };
+  // byte offsets (4 row d) of this lane's rows, relative to row0: S X
+  // holds rows row0 .. row0 + 2^30 / d - 1 of this launch.  Loads clamp to
+  // the chunk's last row (to B - 1 for a wavefront past B, which then
+  // loads once and adds nothing; B - 1 >= row0, since every launch starts
+  // below B)
+  const uint32_t ud = 4u * (uint32_t)d;
+  const uint32_t last = (uint32_t)((kend > kbeg ? kend : B) - 1 - row0) * ud;
+  uint32_t off = (uint32_t)(kbeg + kq * 8 - row0) * ud;
   float xn[8][NB];
-  load_step(kbeg + kq * 8, xn);
+  lowp_load_rows<NB, VEC>(SX, off, ud, last, ccol, xn);
   for (int64_t kb = kbeg; kb < kend; kb += KBLK) {
     float xscale = 1.0f, yscale = 1.0f;
     if constexpr (FP8) {
@@ -407,77 +466,78 @@ __global__ __launch_bounds__(kThreads, 4) void gsx_lowp_kernel(const float* __re
 #pragma unroll
     for (int sub = 0; sub < KBLK / 32; ++sub) {
       const int64_t base = kb + sub * 32 + kq * 8;
+      // rows past the chunk (only in its last step) hold clamped reloads:
+      // zero them.  A zero S X value makes its products with G exactly
+      // zero, so the normals of those columns need no mask of their own
+      // (they are finite, drawn from counters past the chunk).
+      if (kb + sub * 32 + 32 > kend) {   // the same in the whole wavefront
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) xn[e][nb] = base + e < kend ? xn[e][nb] : 0.0f;
+      }
       // this step's S X operand, packed from the values that arrived
-      int xlo[NB], xhi[NB];
-      v8bf xb[NB];
+      uint32_t xw[NB][4];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        xlo[nb] = xhi[nb] = 0;
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
-          const bool ok0 = base + e < kend && cok[nb], ok1 = base + e + 1 < kend && cok[nb];
-          const float x0 = ok0 ? xn[e][nb] : 0.0f, x1 = ok1 ? xn[e + 1][nb] : 0.0f;
+          float x0 = xn[e][nb], x1 = xn[e + 1][nb];
+          if constexpr (!VEC) {
+            x0 = cok[nb] ? x0 : 0.0f;
+            x1 = cok[nb] ? x1 : 0.0f;
+          }
           if constexpr (FP8) {
-            int& w = e < 4 ? xlo[nb] : xhi[nb];
-            w = (e & 2) ? cvt_fp8<true>(x0 * xscale, x1 * xscale, w)
-                        : cvt_fp8<false>(x0 * xscale, x1 * xscale, w);
+            uint32_t& w = xw[nb][e >> 2];
+            w = (e & 2) ? (uint32_t)cvt_fp8<true>(x0 * xscale, x1 * xscale, (int)w)
+                        : (uint32_t)cvt_fp8<false>(x0 * xscale, x1 * xscale, 0);
           } else {
-            xb[nb][e] = (__bf16)x0;
-            xb[nb][e + 1] = (__bf16)x1;
+            xw[nb][e >> 1] = bf16_pair(x0, x1);
           }
         }
       }
-      // the next step's rows (the step after the last is a harmless reload)
-      load_step(base + 32, xn);
-      // G's operand, two columns of B at a time; normals unguarded at
-      // clamped indices, zeroed past the chunk
-      int glo[4] = {0, 0, 0, 0}, ghi[4] = {0, 0, 0, 0};
-      v8bf gb[4];
+      // the next step's rows (past the chunk: clamped reloads of its last row)
+      off += 32 * ud;
+      lowp_load_rows<NB, VEC>(SX, off, ud, last, ccol, xn);
+      // G's operand, two columns of B at a time
+      uint32_t gw[4][4];
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
-        const int64_t b0 = base + e, b1 = b0 + 1;
-        const bool ok0 = b0 < kend, ok1 = b1 < kend;
-        const int64_t c0 = ok0 ? b0 : kend - 1, c1 = ok1 ? b1 : kend - 1;
         float z0[4], z1[4];
-        box_muller(gauss_block((uint32_t)c0, q, key.k0, key.k1), z0);
-        box_muller(gauss_block((uint32_t)c1, q, key.k0, key.k1), z1);
+        box_muller(gauss_block((uint32_t)(base + e), q, key.k0, key.k1), z0, FP8 ? 64.0f : 1.0f);
+        box_muller(gauss_block((uint32_t)(base + e + 1), q, key.k0, key.k1), z1, FP8 ? 64.0f : 1.0f);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          z0[t] = ok0 ? z0[t] : 0.0f;
-          z1[t] = ok1 ? z1[t] : 0.0f;
-        }
-        if constexpr (FP8) {
-          // columns e, e + 1 go to byte pair (e / 2) % 2 of word e / 4
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            int& w = e < 4 ? glo[t] : ghi[t];
-            w = (e & 2) ? cvt_fp8<true>(z0[t] * 64.0f, z1[t] * 64.0f, w)
-                        : cvt_fp8<false>(z0[t] * 64.0f, z1[t] * 64.0f, w);
-          }
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            gb[t][e] = (__bf16)z0[t];
-            gb[t][e + 1] = (__bf16)z1[t];
+          if constexpr (FP8) {
+            // columns e, e + 1 go to byte pair (e / 2) % 2 of word e / 4
+            uint32_t& w = gw[t][e >> 2];
+            w = (e & 2) ? (uint32_t)cvt_fp8<true>(z0[t], z1[t], (int)w)
+                        : (uint32_t)cvt_fp8<false>(z0[t], z1[t], 0);
+          } else {
+            gw[t][e >> 1] = bf16_pair(z0[t], z1[t]);
           }
         }
       }
       if constexpr (FP8) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const long ga = (long)(uint32_t)glo[t] | ((long)(uint32_t)ghi[t] << 32);
+          const long ga = (long)gw[t][0] | ((long)gw[t][1] << 32);
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
-            const long xa = (long)(uint32_t)xlo[nb] | ((long)(uint32_t)xhi[nb] << 32);
+            const long xa = (long)xw[nb][0] | ((long)xw[nb][1] << 32);
             tmp[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ga, xa, tmp[t][nb], 0, 0, 0);
           }
         }
       } else {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t) {
+          const v8bf gb = __builtin_bit_cast(v8bf, u32x4{gw[t][0], gw[t][1], gw[t][2], gw[t][3]});
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb[t], xb[nb], acc[t][nb], 0, 0, 0);
+          for (int nb = 0; nb < NB; ++nb) {
+            const v8bf xb = __builtin_bit_cast(v8bf, u32x4{xw[nb][0], xw[nb][1], xw[nb][2], xw[nb][3]});
+            acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb, xb, acc[t][nb], 0, 0, 0);
+          }
+        }
       }
     }
     if constexpr (FP8) {
@@ -487,8 +547,8 @@ __global__ __launch_bounds__(kThreads, 4) void gsx_lowp_kernel(const float* __re
         for (int nb = 0; nb < NB; ++nb) acc[t][nb] += tmp[t][nb] * yscale;
     }
   }
-  block_reduce_store<float, NB, v4f>(acc, red, wave, lane, group, n0, m, d,
-                                     part + (size_t)blockIdx.x * m * d);
+  block_reduce_store<float, NB, v4f, VEC>(acc, red, wave, lane, group, n0, m, d,
+                                          part + (size_t)bx * m * d);
 }
 
 // Y[o] = sum over partials p of part[p][o]: 16 wavefronts each add a
@@ -797,8 +857,24 @@ void launch_lowp(const GsxPlan& pl, const float* SX, int64_t B, int d, int m, Ke
                                                                                       bscale);
     }
   }
-  dim3 grid((unsigned)pl.parts, (unsigned)pl.mgroups, (unsigned)pl.ngroups);
-  gsx_lowp_kernel<NB, FP8><<<grid, kThreads, 0, s>>>(SX, B, d, m, pl.kc, key, bscale, part);
+  // parts per launch: every row a launch reads (its chunks plus the
+  // prefetch one step past them) lies within 2^30 / d rows of its first,
+  // so byte offsets from that row fit in 32 bits
+  const int64_t rows_per_part = (int64_t)kWaves * pl.kc;
+  const int64_t max_rows = ((int64_t)1 << 30) / d;
+  const int64_t per = max((int64_t)1, max_rows / rows_per_part - 1);
+  const bool vec = (NB == 2 || NB == 4) && d % (16 * NB) == 0;
+  for (int64_t bx0 = 0; bx0 < pl.parts; bx0 += per) {
+    const int64_t np = min(per, pl.parts - bx0);
+    const int64_t row0 = bx0 * rows_per_part;
+    dim3 grid((unsigned)np, (unsigned)pl.mgroups, (unsigned)pl.ngroups);
+    if (vec)
+      gsx_lowp_kernel<NB, FP8, (NB == 2 || NB == 4)><<<grid, kThreads, 0, s>>>(
+          SX + row0 * d, row0, bx0, B, d, m, pl.kc, key, bscale, part);
+    else
+      gsx_lowp_kernel<NB, FP8, false><<<grid, kThreads, 0, s>>>(SX + row0 * d, row0, bx0, B, d, m,
+                                                                pl.kc, key, bscale, part);
+  }
 }
 
 }  // namespace

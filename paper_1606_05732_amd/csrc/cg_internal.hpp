@@ -304,6 +304,10 @@ hipError_t launch_lemma_stats(const T* Y, const T* SU, int64_t m, int64_t B, int
 // 2: write dst.  bytes: a multiple of 16, both pointers 16-byte aligned.
 int stream_blocks();
 hipError_t launch_stream(int kind, const void* src, void* dst, int64_t bytes, hipStream_t s);
+// normals of G's columns [0, B), rows [0, m) (m a multiple of 4); one sum
+// per thread into sink[normals_threads()]
+int normals_threads();
+hipError_t launch_normals_rate(Key key, int64_t m, int64_t B, float* sink, hipStream_t s);
 
 // ---- test access ------------------------------------------------------
 hipError_t launch_debug_philox(Key key, const uint32_t* ctr, int64_t count, uint32_t* out,

@@ -33,15 +33,21 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
+// a ^ b ^ c in one gfx950 v_bitop3_b32 (truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Ten Philox rounds.  The key words are wave-uniform in every caller, so the
-// compiler keeps the key schedule in scalar registers.
+// compiler keeps the key schedule in scalar registers.  Each round is two
+// 32 x 32 -> 64-bit products and two three-way xors.
 __device__ __forceinline__ Words4 philox10(Words4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
-    const Words4 n = {(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                      (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0};
+    const Words4 n = {xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                      xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0};
     c = n;
     k0 += kPhiloxW0;
     k1 += kPhiloxW1;
@@ -106,8 +112,11 @@ __device__ __forceinline__ Words4 dense_gauss_block(uint64_t r, uint32_t q, uint
   return philox10(Words4{(uint32_t)r, q, 2u, (uint32_t)(r >> 32)}, k0, k1);
 }
 
+// 0x3f800000 | (w >> 9) is 1 + (w >> 9) 2^-23 (one v_alignbit_b32);
+// subtracting 1 - 2^-24 leaves ((w >> 9) + 1/2) 2^-23 exactly (both
+// operands and the difference are representable: Sterbenz).
 __device__ __forceinline__ float unit_f32(uint32_t w) {
-  return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, w, 9u)) - 0x1.fffffep-1f;
 }
 __device__ __forceinline__ double unit_f64(uint32_t w) {
   return ((double)(w >> 9) + 0.5) * 0x1p-23;
@@ -120,10 +129,13 @@ __device__ __forceinline__ double unit_f64(uint32_t w) {
 // absolute error 8.5e-7, rms 6.1e-8 -- about what the device library's
 // logf/sqrtf/sincospif give (7.4e-7, 5.1e-8), since the error is dominated
 // by u itself being FP32 -- at three times the rate.
-__device__ __forceinline__ void box_muller(const Words4& w, float z[4]) {
+// `rscale` (a power of two) scales the radii, and so the four normals,
+// exactly: the reduced-precision contraction draws G 2^6 for its FP8
+// operand at the cost of two multiplies instead of four.
+__device__ __forceinline__ void box_muller(const Words4& w, float z[4], float rscale = 1.0f) {
   constexpr float kNeg2Ln2 = -1.3862943611198906f;
-  const float r0 = __builtin_amdgcn_sqrtf(kNeg2Ln2 * __builtin_amdgcn_logf(unit_f32(w.x)));
-  const float r1 = __builtin_amdgcn_sqrtf(kNeg2Ln2 * __builtin_amdgcn_logf(unit_f32(w.z)));
+  const float r0 = rscale * __builtin_amdgcn_sqrtf(kNeg2Ln2 * __builtin_amdgcn_logf(unit_f32(w.x)));
+  const float r1 = rscale * __builtin_amdgcn_sqrtf(kNeg2Ln2 * __builtin_amdgcn_logf(unit_f32(w.z)));
   const float u1 = unit_f32(w.y), u3 = unit_f32(w.w);
   z[0] = r0 * __builtin_amdgcn_cosf(u1);
   z[1] = r0 * __builtin_amdgcn_sinf(u1);

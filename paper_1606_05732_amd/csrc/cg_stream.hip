@@ -4,6 +4,7 @@
 // 16-byte accesses, consecutive lanes on consecutive addresses, eight
 // accesses in flight per lane, over a grid of 32 workgroups per CU.
 #include "cg_internal.hpp"
+#include "cg_rng.hpp"
 
 namespace cg {
 
@@ -80,9 +81,47 @@ __global__ __launch_bounds__(kThreads) void stream_write_kernel(u32x4* __restric
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) st<NT>(dst + i, v);
 }
 
+// The generator's own ceiling: the normals of G for columns [0, B) and
+// row quads [0, m / 4) (Philox4x32-10 of counter (b, q, 1, 0), FP32
+// Box-Muller, exactly as the contractions draw them), with nothing else:
+// each thread adds up its normals and writes one sum.  Thread t takes the
+// blocks t, t + T, ... (T threads), eight in flight.
+__global__ __launch_bounds__(kThreads) void normals_rate_kernel(Key key, uint32_t quads, int64_t B,
+                                                                float* __restrict__ sink) {
+  const int64_t T = (int64_t)gridDim.x * kThreads;
+  const int64_t t0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t nblk = B * quads;
+  constexpr int U = 8;
+  float acc = 0.0f;
+  int64_t i = t0;
+  for (; i + (U - 1) * T < nblk; i += U * T) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = i + u * T;
+      float z[4];
+      box_muller(gauss_block((uint32_t)(k / quads), (uint32_t)(k % quads), key.k0, key.k1), z);
+      acc += (z[0] + z[1]) + (z[2] + z[3]);
+    }
+  }
+  for (; i < nblk; i += T) {
+    float z[4];
+    box_muller(gauss_block((uint32_t)(i / quads), (uint32_t)(i % quads), key.k0, key.k1), z);
+    acc += (z[0] + z[1]) + (z[2] + z[3]);
+  }
+  sink[t0] = acc;
+}
+
 }  // namespace
 
 int stream_blocks() { return 256 * 32; }
+
+int normals_threads() { return 256 * 32 * kThreads; }
+
+hipError_t launch_normals_rate(Key key, int64_t m, int64_t B, float* sink, hipStream_t s) {
+  normals_rate_kernel<<<(unsigned)stream_blocks(), kThreads, 0, s>>>(key, (uint32_t)(m / 4), B,
+                                                                     sink);
+  return hipGetLastError();
+}
 
 hipError_t launch_stream(int kind, const void* src, void* dst, int64_t bytes, hipStream_t s) {
   const int64_t n = bytes / 16;

@@ -984,16 +984,37 @@ __device__ __forceinline__ void for_range_items(const uint2* __restrict__ items,
 // amax <= 448 2^e (at least -100), the same rule as the contraction's own
 // scale kernel.  Ranges hold whole blocks (2^bp_shift >= 128 buckets, which
 // bin_geometry gives whenever d <= 64); `value(c)` is cell c's FP32 value.
+// A block spans 128 d cells, a multiple of 64, and the cells are taken
+// thread-strided by a multiple of 64, so the 64 cells a wavefront holds at
+// each step lie in one block: each wavefront keeps its running maximum per
+// block and adds it with one LDS atomic when its block changes (one atomic
+// per cell, on a handful of words, serialises badly).
 template <typename F>
 __device__ __forceinline__ void emit_fp8_scales(const BinArgs& a, int p, int cells, F&& value,
                                                 uint32_t* s_amax) {
+  static_assert(kThreads % 64 == 0, "whole wavefronts");
   const int d = a.d, nblk = (1 << a.bp_shift) / 128;
   for (int i = threadIdx.x; i < nblk; i += kThreads) s_amax[i] = 0u;
   __syncthreads();
+  // NaNs are skipped; |v| >= 0, so the unsigned order of the bits is the
+  // float order
+  uint32_t run = 0u;
+  int cur = -1;
+  auto flush = [&]() {
+    for (int off = 32; off > 0; off >>= 1) run = max(run, (uint32_t)__shfl_xor((int)run, off, 64));
+    if ((threadIdx.x & 63) == 0 && cur >= 0 && run) atomicMax(&s_amax[cur], run);
+  };
   for (int c = threadIdx.x; c < cells; c += kThreads) {
+    const int blk = (c / d) >> 7;   // the same in every lane of the wavefront
+    if (blk != cur) {
+      flush();
+      cur = blk;
+      run = 0u;
+    }
     const float v = fabsf(value(c));
-    if (v == v) atomicMax(&s_amax[(c / d) >> 7], __float_as_uint(v));
+    if (v == v) run = max(run, __float_as_uint(v));
   }
+  flush();
   __syncthreads();
   for (int i = threadIdx.x; i < nblk; i += kThreads) {
     const int64_t blk = (((int64_t)p << a.bp_shift) >> 7) + i;
@@ -1013,8 +1034,10 @@ __device__ __forceinline__ void emit_fp8_scales(const BinArgs& a, int p, int cel
 
 // FUSED: the range's S X slice goes to `slice` in LDS (float, cells
 // thread-strided as in s_acc, zero past B) instead of to a.SX, for the
-// fused contraction that follows.
-template <bool FUSED = false>
+// fused contraction that follows.  EMIT: a.fp8_scale is set, and the
+// range's FP8 block scales are written too (a separate instance, so that
+// the other launches carry none of that code or its registers).
+template <bool FUSED = false, bool EMIT = false>
 __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p, float* slice = nullptr) {
   const uint2* __restrict__ items = a.items;
   const uint32_t* __restrict__ tot = a.tot;
@@ -1052,7 +1075,7 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p, float*
       else if (bucket < B)
         SX[bucket * d + i % d] = acc[i];
     }
-    if constexpr (!FUSED) {
+    if constexpr (EMIT && !FUSED) {
       if (a.fp8_scale)
         emit_fp8_scales(a, p, cells, [&](int c) {
           const int64_t bucket = ((int64_t)p << bp_shift) + c / d;
@@ -1107,7 +1130,7 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p, float*
       else if (bucket < B)
         SX[bucket * d + c % d] = v;
     }
-    if constexpr (!FUSED) {
+    if constexpr (EMIT && !FUSED) {
       if (a.fp8_scale)
         emit_fp8_scales(a, p, cells, [&](int c) {
           const int64_t bucket = ((int64_t)p << bp_shift) + c / d;
@@ -1147,7 +1170,7 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p, float*
     else if (bucket < B)
       SX[bucket * d + c % d] = v;
   }
-  if constexpr (!FUSED) {
+  if constexpr (EMIT && !FUSED) {
     if (a.fp8_scale) {
       // the range's values were written by this workgroup: read them back
       __syncthreads();
@@ -1249,8 +1272,11 @@ __device__ __forceinline__ void fused_contract(const BinArgs& a, int p, const fl
   }
 }
 
-__global__ __launch_bounds__(kThreads) void bin_reduce_csr_kernel(BinArgs a) {
-  reduce_csr_range(a, blockIdx.x);
+// Two workgroups per CU when the ranges' LDS allows it (the batched
+// launch's small ranges do): eight waves per SIMD, 64 registers per lane.
+template <bool EMIT>
+__global__ __launch_bounds__(kThreads, 8) void bin_reduce_csr_kernel(BinArgs a) {
+  reduce_csr_range<false, EMIT>(a, blockIdx.x);
 }
 
 // LDS of the fused kernel: the range's fixed-point sums (64 KB, reused for
@@ -1476,7 +1502,7 @@ __global__ __launch_bounds__(kSThreads, 4) void bin_scatter_batched(const BinArg
   scatter_csr_tile(a, (int64_t)blockIdx.x - first[i]);
 }
 
-__global__ __launch_bounds__(kThreads) void bin_reduce_batched(const BinArgs* __restrict__ args,
+__global__ __launch_bounds__(kThreads, 8) void bin_reduce_batched(const BinArgs* __restrict__ args,
                                                                const int32_t* __restrict__ inst,
                                                                const int32_t* __restrict__ first) {
   const int i = inst[blockIdx.x];
@@ -1558,12 +1584,16 @@ hipError_t launch_sx_binned_csr(const int32_t* row_ptr, const int32_t* col_idx, 
   hipError_t e;
   if ((e = allow_lds(bin_count_kernel<true>, cl)) != hipSuccess) return e;
   if ((e = allow_lds(bin_scatter_csr_kernel, sl)) != hipSuccess) return e;
-  if ((e = allow_lds(bin_reduce_csr_kernel, g.lds_bytes)) != hipSuccess) return e;
+  if ((e = allow_lds(bin_reduce_csr_kernel<false>, g.lds_bytes)) != hipSuccess) return e;
+  if ((e = allow_lds(bin_reduce_csr_kernel<true>, g.lds_bytes)) != hipSuccess) return e;
   bin_count_kernel<true><<<(unsigned)g.ntiles, kCntThreads, cl, s>>>(a);
   bin_scan_kernel<<<(unsigned)g.R, kSThreads, 0, s>>>(a);
   if (events && events[1] && (e = hipEventRecord((hipEvent_t)events[1], s)) != hipSuccess) return e;
   bin_scatter_csr_kernel<<<(unsigned)g.ntiles, kSThreads, sl, s>>>(a);
-  bin_reduce_csr_kernel<<<(unsigned)g.R, kThreads, g.lds_bytes, s>>>(a);
+  if (a.fp8_scale)
+    bin_reduce_csr_kernel<true><<<(unsigned)g.R, kThreads, g.lds_bytes, s>>>(a);
+  else
+    bin_reduce_csr_kernel<false><<<(unsigned)g.R, kThreads, g.lds_bytes, s>>>(a);
   return hipGetLastError();
 }
 

@@ -63,3 +63,17 @@ def test_gaussian_matches_oracle(cuda, m, b0, nb):
     err = np.abs(G32 - ref)
     assert np.max(err) < 1.5e-6, np.max(err)
     assert np.max(np.abs(G32)) <= O.GAUSS_ABS_MAX
+
+
+@pytest.mark.parametrize("m,B", [(4, 1), (64, 4096), (8, 262145)])
+def test_normals_probe_draws_g(cuda, m, B):
+    """The generator-only probe draws exactly the normals of G: its
+    per-thread sums add up to the sum of the device's G (FP32, different
+    order: a rounding-level tolerance) and of the oracle's."""
+    say("normals probe", m, B)
+    sink = cg.debug_normals(77, m, B, cuda).cpu().numpy().astype(np.float64)
+    G = cg.debug_gaussian(77, m, 0, B, torch.float32, cuda).cpu().numpy().astype(np.float64)
+    ref = O.gaussian_block(77, m, 0, B)
+    tol = 1e-5 * np.sum(np.abs(ref)) + 1e-6
+    assert abs(sink.sum() - G.sum()) < tol
+    assert abs(sink.sum() - ref.sum()) < tol
