@@ -187,12 +187,11 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
   T xn[KU][NB];
   load_group(kbeg, xn);
   // full groups: the normals of the first step (later ones are drawn a
-  // step ahead, below)
+  // step ahead, below).  Normals of columns past the chunk need no mask:
+  // their S X operand is zeroed, and a finite normal times zero adds
+  // nothing; their counters are just numbers, so they need no clamp.
   T gn[4];
-  if constexpr (!HALF) {
-    const int64_t b = kbeg + kq;
-    box_muller(k_block<TAG>(b < kend ? b : kend - 1, col0, q, key), gn);
-  }
+  if constexpr (!HALF) box_muller(k_block<TAG>(kbeg + kq, col0, q, key), gn);
   for (int64_t kg = kbeg; kg < kend; kg += 4 * KU) {
     T x[KU][NB];
 #pragma unroll
@@ -205,13 +204,11 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
       for (int u = 0; u < KU; u += 2) {
         // this lane's normals: step u (p < 8) or step u + 1 (p >= 8)
         const int64_t bg = kg + 4 * (u + (p >> 3)) + kq;
-        const bool gok = bg < kend;
         T g[4];
-        box_muller(k_block<TAG>(gok ? bg : kend - 1, col0, q, key), g);
+        box_muller(k_block<TAG>(bg, col0, q, key), g);
         T a0[4], a1[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          g[t] = gok ? g[t] : T(0);
           a0[t] = p < 8 ? g[t] : T(0);
           a1[t] = from_lane_p8(g[t]);
         }
@@ -238,11 +235,8 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
         // step's MFMAs
         T g[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) g[t] = bok ? gn[t] : T(0);
-        {
-          const int64_t bn = b + 4;
-          box_muller(k_block<TAG>(bn < kend ? bn : kend - 1, col0, q, key), gn);
-        }
+        for (int t = 0; t < 4; ++t) g[t] = gn[t];
+        box_muller(k_block<TAG>(b + 4, col0, q, key), gn);
         T xv[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) xv[nb] = bok && col[nb] < d ? x[u][nb] : T(0);
