@@ -1188,13 +1188,14 @@ __device__ __forceinline__ void reduce_csr_range(const BinArgs& a, int p, float*
 // multiplied at once by the columns of G of the range's buckets (generated
 // in registers), so S X never reaches memory; each range leaves one partial
 // m x d product, and the split reduction adds the R partials in range
-// order (bitwise reproducible).  Four wavefronts take a quarter of the
-// range's buckets each, in steps of four on 16x16x4 FP32 MFMA with the
-// contraction kernel's register tiling (lane (p, kq): G rows 4 q + t of
-// quad q = 16 group + p, K slot kq); for every 64-row group of G and
-// 16 NB-column group of S X in turn, waves 1 .. 3 hand their accumulators
-// to wave 0 through LDS, which adds them in order and writes the partial.
-constexpr int kFusedWaves = 4;
+// order (bitwise reproducible).  All sixteen wavefronts take a sixteenth
+// of the range's buckets each, in steps of four on 16x16x4 FP32 MFMA with
+// the contraction kernel's register tiling (lane (p, kq): G rows 4 q + t of
+// quad q = 16 group + p, K slot kq).  For every 64-row group of G and
+// 16 NB-column group of S X in turn, the sixteen accumulators are added in
+// a fixed tree through LDS (wave w + h into wave w, h = 8, 4, 2, 1, two
+// column blocks at a time), and wave 0 writes the partial.
+constexpr int kFusedWaves = kThreads / 64;
 
 template <int NB>
 __device__ __forceinline__ void fused_contract(const BinArgs& a, int p, const float* slice,
@@ -1209,6 +1210,8 @@ __device__ __forceinline__ void fused_contract(const BinArgs& a, int p, const fl
   const int kbeg = wave * kc, kend = min(kbeg + kc, Bp);
   float* __restrict__ out = a.part + (size_t)p * m * d;
   const int mgroups = (m + 63) / 64, ngroups = (d + 16 * NB - 1) / (16 * NB);
+  constexpr int NBC = NB < 2 ? NB : 2;   // column blocks per reduction pass
+  constexpr int kV = 16 * NBC;           // values per lane per pass
   for (int g = 0; g < mgroups; ++g) {
     const uint32_t q = (uint32_t)(16 * g + pl);
     for (int ng = 0; ng < ngroups; ++ng) {
@@ -1218,39 +1221,53 @@ __device__ __forceinline__ void fused_contract(const BinArgs& a, int p, const fl
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
-      if (wave < kFusedWaves) {
-        for (int k0 = kbeg; k0 < kend; k0 += 4) {
-          const int bl = k0 + kq;
-          const int64_t bucket = bucket0 + bl;
-          const bool ok = bl < kend && bucket < (int64_t)a.B;
-          float z[4];
-          box_muller(gauss_block((uint32_t)(ok ? bucket : bucket0), q, a.key.k0, a.key.k1), z);
-          float x[NB];
+      for (int k0 = kbeg; k0 < kend; k0 += 4) {
+        const int bl = k0 + kq;
+        const int64_t bucket = bucket0 + bl;
+        const bool ok = bl < kend && bucket < (int64_t)a.B;
+        // a zero S X operand makes the normals of a column past the range
+        // or past B add nothing, so they need no mask
+        float z[4];
+        box_muller(gauss_block((uint32_t)bucket, q, a.key.k0, a.key.k1), z);
+        float x[NB];
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const int c = n0 + nb * 16 + pl;
-            x[nb] = ok && c < d ? slice[bl * d + c] : 0.0f;
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const float gt = ok ? z[t] : 0.0f;
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gt, x[nb], acc[t][nb], 0, 0, 0);
-          }
+        for (int nb = 0; nb < NB; ++nb) {
+          const int c = n0 + nb * 16 + pl;
+          x[nb] = ok && c < d ? slice[bl * d + c] : 0.0f;
         }
-      }
-      constexpr int kVals = 16 * NB;   // accumulator values per lane
-      if (wave > 0 && wave < kFusedWaves) {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              red[((wave - 1) * kVals + (t * NB + nb) * 4 + r) * 64 + lane] = acc[t][nb][r];
+            acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(z[t], x[nb], acc[t][nb], 0, 0, 0);
       }
-      __syncthreads();
+      for (int h = kFusedWaves / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int nb0 = 0; nb0 < NB; nb0 += NBC) {
+          if (wave >= h && wave < 2 * h) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int c = 0; c < NBC; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  if (nb0 + c < NB)
+                    red[((wave - h) * kV + (t * NBC + c) * 4 + r) * 64 + lane] = acc[t][nb0 + c][r];
+          }
+          __syncthreads();
+          if (wave < h) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int c = 0; c < NBC; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  if (nb0 + c < NB)
+                    acc[t][nb0 + c][r] += red[(wave * kV + (t * NBC + c) * 4 + r) * 64 + lane];
+          }
+          __syncthreads();   // red is reused by the next pass
+        }
+      }
       if (wave == 0) {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -1258,16 +1275,11 @@ __device__ __forceinline__ void fused_contract(const BinArgs& a, int p, const fl
           for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int idx = (t * NB + nb) * 4 + r;
-              float sum = acc[t][nb][r];
-#pragma unroll
-              for (int w = 0; w < kFusedWaves - 1; ++w) sum += red[(w * kVals + idx) * 64 + lane];
               const int row = 4 * (16 * g + 4 * kq + r) + t;
               const int col = n0 + nb * 16 + pl;
-              if (row < m && col < d) out[(size_t)row * d + col] = sum;
+              if (row < m && col < d) out[(size_t)row * d + col] = acc[t][nb][r];
             }
       }
-      __syncthreads();   // red is reused by the next group
     }
   }
 }
@@ -1282,8 +1294,8 @@ __global__ __launch_bounds__(kThreads, 8) void bin_reduce_csr_kernel(BinArgs a) 
 // LDS of the fused kernel: the range's fixed-point sums (64 KB, reused for
 // the cross-wave sums of the contraction) | its FP32 slice (32 KB)
 constexpr size_t kFusedLds = (size_t)kCsrMaxCells * 8 + (size_t)kCsrMaxCells * 4;
-static_assert((size_t)(kFusedWaves - 1) * 16 * 4 * 64 * 4 <= (size_t)kCsrMaxCells * 8,
-              "the cross-wave sums fit in the fixed-point area");
+static_assert((size_t)(kFusedWaves / 2) * 16 * 2 * 64 * 4 <= (size_t)kCsrMaxCells * 8,
+              "a pass of the cross-wave tree fits in the fixed-point area");
 
 template <int NB>
 __global__ __launch_bounds__(kThreads) void bin_reduce_fused_kernel(BinArgs a) {
