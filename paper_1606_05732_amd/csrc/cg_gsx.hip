@@ -20,12 +20,15 @@
 // D rows of a lane are kq + 4 r instead, see d_row).
 //
 // Half groups: when a 64-row group holds at most 32 rows of G (m <= 32,
-// or the last group), only lanes p < 8 own rows that exist.  Lanes
-// p >= 8 then generate, for the row quad of lane p - 8, the normals of the
-// next step's columns, and a lane move (p + 8 -> p) hands them down: every
-// lane draws one Philox block per two steps, and the MFMAs see the same
-// operands in the same order as in a full group (rows >= 32 zero), so the
-// result is bit for bit the same.
+// or the last group), its row quads are q = 16 group + (p & 7).  Lanes
+// p < 8 draw a step's normals and lanes p >= 8 the next step's, for the
+// same quads, so every lane draws one Philox block per two steps.  Rows
+// are paired in two M blocks: block 0 holds rows 4q (lanes p < 8) and
+// 4q + 1 (lanes p >= 8), block 1 rows 4q + 2 and 4q + 3, with lane moves
+// (p - 8 -> p, p + 8 -> p) bringing each normal to its lane.  That is half
+// the MFMAs of four blocks with the upper half idle, and every existing
+// row still sees the same operands in the same order as in a full group,
+// so the result is bit for bit the same.
 #include "cg_internal.hpp"
 #include "cg_rng.hpp"
 
@@ -71,15 +74,18 @@ __device__ __forceinline__ int d_row(int kq, int r) {
 // order) and write the workgroup's partial product rows/cols that exist.
 // VEC: lane p's NB column blocks hold the consecutive columns
 // n0 + NB p + nb (so that one vector load fetches them) instead of
-// n0 + 16 nb + p.
-template <typename T, int NB, typename V, bool VEC = false>
+// n0 + 16 nb + p.  PAIRS: the half-group layout, two M blocks (acc[0],
+// acc[1]) whose row i holds G row 4 (16 group + i) + 2 t for i < 8 and
+// 4 (16 group + i - 8) + 2 t + 1 for i >= 8.
+template <typename T, int NB, typename V, bool VEC = false, bool PAIRS = false>
 __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int wave, int lane,
                                                    int group, int n0, int m, int d,
                                                    T* __restrict__ out) {
   constexpr int R = 16 * NB;   // accumulator values per lane
+  constexpr int MB = PAIRS ? 2 : 4;
   if (wave > 0) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < MB; ++t)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -90,7 +96,7 @@ __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int 
   if (wave != 0) return;
   const int p = lane & 15, kq = lane >> 4;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < MB; ++t)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -100,7 +106,9 @@ __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int 
         s += red[(0 * R + idx) * 64 + lane];
         s += red[(1 * R + idx) * 64 + lane];
         s += red[(2 * R + idx) * 64 + lane];
-        const int row = 4 * (16 * group + d_row<T>(kq, r)) + t;
+        const int i = d_row<T>(kq, r);
+        const int row = PAIRS ? (i < 8 ? 4 * (16 * group + i) + 2 * t : 4 * (16 * group + i - 8) + 2 * t + 1)
+                              : 4 * (16 * group + i) + t;
         const int col = VEC ? n0 + NB * p + nb : n0 + nb * 16 + p;
         if (row < m && col < d) out[(size_t)row * d + col] = s;
       }
@@ -117,6 +125,16 @@ __device__ __forceinline__ float from_lane_p8(float v) {
 __device__ __forceinline__ double from_lane_p8(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x108, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x108, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// Lane p - 8's value in lane p of each 16-lane row (0 in lanes 0 .. 7):
+// DPP row_shr:8.
+__device__ __forceinline__ float from_lane_m8(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_lane_m8(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x118, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x118, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -202,16 +220,19 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
     if constexpr (HALF) {
 #pragma unroll
       for (int u = 0; u < KU; u += 2) {
-        // this lane's normals: step u (p < 8) or step u + 1 (p >= 8)
+        // this lane's normals: step u (p < 8) or step u + 1 (p >= 8), both
+        // for row quad q = 16 group + (p & 7)
         const int64_t bg = kg + 4 * (u + (p >> 3)) + kq;
         T g[4];
         box_muller(k_block<TAG>(bg, col0, q, key), g);
-        T a0[4], a1[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          a0[t] = p < 8 ? g[t] : T(0);
-          a1[t] = from_lane_p8(g[t]);
-        }
+        // two M blocks of paired rows: block 0 holds rows 4q (lanes p < 8)
+        // and 4q + 1 (lanes p >= 8), block 1 rows 4q + 2 and 4q + 3.  Step
+        // u's normals come from lanes p < 8, step u + 1's from lanes p >= 8,
+        // each moved to the other half of the row where needed
+        const T m1 = from_lane_m8(g[1]), m3 = from_lane_m8(g[3]);
+        const T p0 = from_lane_p8(g[0]), p2 = from_lane_p8(g[2]);
+        const bool lo = p < 8;
+        const T a[2][2] = {{lo ? g[0] : m1, lo ? g[2] : m3}, {lo ? p0 : g[1], lo ? p2 : g[3]}};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           // S X rows of step u + h (this lane's K slot kq, as in a full group)
@@ -220,9 +241,9 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) xv[nb] = bok && col[nb] < d ? x[u + h][nb] : T(0);
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
+          for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(h ? a1[t] : a0[t], xv[nb], acc[t][nb]);
+            for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(a[h][t], xv[nb], acc[t][nb]);
         }
       }
     } else {
@@ -247,7 +268,8 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
       }
     }
   }
-  block_reduce_store<T, NB, V>(acc, red, wave, lane, group, n0, m, d, part + (size_t)bx * m * d);
+  block_reduce_store<T, NB, V, false, HALF>(acc, red, wave, lane, group, n0, m, d,
+                                            part + (size_t)bx * m * d);
 }
 
 template <typename T, int NB, int TAG>
@@ -758,27 +780,40 @@ __device__ __forceinline__ void gx_rows_block(const GsxArgs& a, int64_t bx, int 
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) g[t] *= sg;
+        if constexpr (HALF) {
+          // paired M blocks as in the contraction kernel's half groups: rows
+          // 4q, 4q + 1 and 4q + 2, 4q + 3, lanes p < 8 holding step h = 0's
+          // rows and p >= 8 step h = 1's
+          const float m1 = from_lane_m8(g[1]), m3 = from_lane_m8(g[3]);
+          const float p0 = from_lane_p8(g[0]), p2 = from_lane_p8(g[2]);
+          const bool lo = p < 8;
+          const float av[2][2] = {{lo ? g[0] : m1, lo ? g[2] : m3}, {lo ? p0 : g[1], lo ? p2 : g[3]}};
 #pragma unroll
-        for (int h = 0; h < (HALF ? 2 : 1); ++h) {
-          float av[4];
+          for (int h = 0; h < 2; ++h) {
+            float xv[NB];
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            av[t] = !HALF ? g[t] : h ? from_lane_p8(g[t]) : (p < 8 ? g[t] : 0.0f);
+            for (int nb = 0; nb < NB; ++nb) xv[nb] = tile[(s0 + 4 * h + kq) * 64 + nb * 16 + p];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(av[h][t], xv[nb], acc[t][nb]);
+          }
+        } else {
           float xv[NB];
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) xv[nb] = tile[(s0 + 4 * h + kq) * 64 + nb * 16 + p];
+          for (int nb = 0; nb < NB; ++nb) xv[nb] = tile[(s0 + kq) * 64 + nb * 16 + p];
 #pragma unroll
           for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(av[t], xv[nb], acc[t][nb]);
+            for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(g[t], xv[nb], acc[t][nb]);
         }
       }
       wave_sync();   // the tile's reads come before the next phase's zeroing
     }
   }
   __syncthreads();   // every wavefront is done with its LDS before the block reduction reuses it
-  block_reduce_store<float, NB, v4f>(acc, lds, wave, lane, group, n0, m, d,
-                                     a.part + (size_t)bx * m * d);
+  block_reduce_store<float, NB, v4f, false, HALF>(acc, lds, wave, lane, group, n0, m, d,
+                                                  a.part + (size_t)bx * m * d);
 }
 
 template <int NB, int TAG>
