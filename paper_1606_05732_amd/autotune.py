@@ -69,3 +69,37 @@ def autotune_batched(items, rows_candidates=(4096, 8192, 16384, 32768),
                 api.set_tuning(rows, kc)
     return {"classes": classes, "rows_per_item": rows, "kc_per_item": kc, "ms_before": base,
             "ms_after": best, "trials": trials, "seconds": time.perf_counter() - t0}
+
+
+def choose_algo(X, m, B, seed, precision="native", candidates=("binned", "atomic", "rows", "fused",
+                                                                 "sorted"),
+                reps=3, warmup=1, row_offset=0):
+    """Measured choice of the S X algorithm for one call shape: each
+    candidate the library accepts for these inputs is planned and timed
+    (whole forward calls, HIP events on the current stream, `reps` runs
+    after `warmup`), and the fastest is returned with every timing:
+    {"algo": name, "ms": {name: ms per call}, "rejected": {name: reason}}.
+    AUTO's static cost model picks without timing; this is the measured
+    alternative for callers that sketch one shape many times."""
+    from ._lib import CountGaussError
+    ms, rejected = {}, {}
+    for algo in candidates:
+        try:
+            plan = api.SketchPlan(X, m, B, seed, precision=precision, algo=algo,
+                                  row_offset=row_offset)
+            for _ in range(warmup):
+                plan.run()
+        except CountGaussError as e:
+            rejected[algo] = str(e)
+            continue
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            plan.run()
+        stop.record()
+        stop.synchronize()
+        ms[algo] = start.elapsed_time(stop) / reps
+        del plan
+    if not ms:
+        raise RuntimeError(f"no S X algorithm accepted these inputs: {rejected}")
+    return {"algo": min(ms, key=ms.get), "ms": ms, "rejected": rejected}

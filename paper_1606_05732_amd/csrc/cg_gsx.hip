@@ -185,8 +185,8 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) ccol[nb] = min(col[nb], d - 1);
   // Groups of KU steps of 4 columns (kc is a multiple of 4 KU).  A group's
-  // S X values are loaded one group ahead, so their latency hides behind
-  // the previous group's normals and MFMAs.  Loads and normals are taken
+  // S X values are loaded two groups ahead, so their latency hides behind
+  // the two previous groups' normals and MFMAs.  Loads and normals are taken
   // unguarded at a clamped index and the values past the chunk or the
   // columns zeroed afterwards (a guarded load would be waited for at the
   // end of its branch).
@@ -202,8 +202,9 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
   };
   // (unconditional: indices clamp to kend - 1 >= 0, and the group after
   // the last is a harmless reload)
-  T xn[KU][NB];
+  T xn[KU][NB], xn2[KU][NB];
   load_group(kbeg, xn);
+  load_group(kbeg + 4 * KU, xn2);
   // full groups: the normals of the first step (later ones are drawn a
   // step ahead, below).  Normals of columns past the chunk need no mask:
   // their S X operand is zeroed, and a finite normal times zero adds
@@ -215,8 +216,11 @@ __device__ __forceinline__ void gsx_native_block(const T* __restrict__ SX, int64
 #pragma unroll
     for (int u = 0; u < KU; ++u)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x[u][nb] = xn[u][nb];
-    load_group(kg + 4 * KU, xn);
+      for (int nb = 0; nb < NB; ++nb) {
+        x[u][nb] = xn[u][nb];
+        xn[u][nb] = xn2[u][nb];
+      }
+    load_group(kg + 8 * KU, xn2);
     if constexpr (HALF) {
 #pragma unroll
       for (int u = 0; u < KU; u += 2) {
