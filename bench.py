@@ -188,7 +188,7 @@ def cpu_baseline(w):
                       f"{t:.2f} s per run, numpy FP64; host has {os.cpu_count()} logical CPUs"}
 
 
-_BASELINE = {}   # the workload and S X, inherited by the forked workers
+_CPU_JOB = {}   # the workload and S X, inherited by the forked workers
 
 
 def _oracle_sx_rows(block):
@@ -196,7 +196,7 @@ def _oracle_sx_rows(block):
     the block's global row offset (S X is linear in the rows, so the
     blocks' results add up to the whole)."""
     import oracle as O
-    w, (a, b) = _BASELINE["w"], block
+    w, (a, b) = _CPU_JOB["w"], block
     c = w.csr
     k0, k1 = int(c.row_ptr[a]), int(c.row_ptr[b])
     return O.sx_csr(c.row_ptr[a:b + 1] - k0, c.col_idx[k0:k1], c.vals[k0:k1], b - a, c.d, w.seed,
@@ -207,7 +207,7 @@ def _oracle_g_cols(block):
     """G[:, a:b] (S X)[a:b] by the oracle's gaussian_block: one column block
     of the product G (S X)."""
     import oracle as O
-    w, SX, (a, b) = _BASELINE["w"], _BASELINE["SX"], block
+    w, SX, (a, b) = _CPU_JOB["w"], _CPU_JOB["SX"], block
     return O.gaussian_block(w.seed, w.m, a, b - a) @ SX[a:b]
 
 
@@ -224,15 +224,15 @@ def cpu_baseline_all_cores(w, procs):
     rb = np.linspace(0, c.n, procs + 1).astype(np.int64)
     cb = np.linspace(0, w.B, procs + 1).astype(np.int64)
     ctx = mp.get_context("fork")
-    _BASELINE["w"] = w
+    _CPU_JOB["w"] = w
     t0 = time.perf_counter()
     with ctx.Pool(procs) as pool:
         SX = sum(pool.map(_oracle_sx_rows, [(int(a), int(b)) for a, b in zip(rb[:-1], rb[1:])]))
-    _BASELINE["SX"] = SX
+    _CPU_JOB["SX"] = SX
     with ctx.Pool(procs) as pool:
         Y = sum(pool.map(_oracle_g_cols, [(int(a), int(b)) for a, b in zip(cb[:-1], cb[1:])]))
     t = time.perf_counter() - t0
-    _BASELINE.clear()
+    _CPU_JOB.clear()
     ref = O.sketch_csr(c.row_ptr, c.col_idx, c.vals, c.n, c.d, w.m, w.B, w.seed)
     assert O.rel_frobenius(Y, ref) < 1e-12
     return {"value": c.nnz / t, "unit": "nnz/s", "cores": procs, "kind": "oracle",
@@ -754,8 +754,8 @@ def main():
                     help="only run a 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the transform shards by rows with one m x d all-reduce; see DESIGN.md)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the transform shards by rows with one m x d all-reduce per call)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -56,7 +56,7 @@ extern "C" {
 #define CG_OK 0
 #define CG_EINVAL 1         /* bad size, null pointer, unknown enum        */
 #define CG_ENOSPACE 2       /* workspace missing or smaller than required  */
-#define CG_EUNSUPPORTED 3   /* valid but outside this build (e.g. d > 1024) */
+#define CG_EUNSUPPORTED 3   /* valid, but outside what the library supports (e.g. d > 1024) */
 #define CG_EHIP 4           /* a HIP runtime call failed (message kept)    */
 
 /* ---- element type of X / Y / dY / dX / S X ---------------------------- */

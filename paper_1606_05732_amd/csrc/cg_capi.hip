@@ -361,7 +361,7 @@ const char* cg_status_string(int status) {
     case CG_OK: return "CG_OK";
     case CG_EINVAL: return "CG_EINVAL (invalid argument)";
     case CG_ENOSPACE: return "CG_ENOSPACE (workspace too small)";
-    case CG_EUNSUPPORTED: return "CG_EUNSUPPORTED (outside this build)";
+    case CG_EUNSUPPORTED: return "CG_EUNSUPPORTED (outside what the library supports)";
     case CG_EHIP: return "CG_EHIP (HIP runtime error)";
     default: return "unknown status";
   }

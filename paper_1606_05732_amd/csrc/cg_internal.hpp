@@ -17,7 +17,7 @@ inline Key key_of(uint64_t seed) { return Key{(uint32_t)seed, (uint32_t)(seed >>
 void set_last_error(const char* msg);
 
 constexpr int kRowsPerWave = 256;   // rows hashed and handled per wavefront
-constexpr int kMaxD = 1024;         // widest X supported by this build
+constexpr int kMaxD = 1024;         // widest X the library supports
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
