@@ -308,9 +308,21 @@ __device__ __forceinline__ void count_tile(const BinArgs& a, int64_t tile) {
   for (int p = threadIdx.x; p < R; p += kCntThreads) a.hist[(int64_t)p * a.ntiles + tile] = s_cnt[p];
 }
 
+// The tile a workgroup takes, so that consecutive tiles run on one XCD:
+// workgroups go to the eight XCDs in turn (workgroup b to XCD b % 8), and
+// XCD x's j-th workgroup takes tile start(x) + j, the XCDs holding
+// contiguous runs of tiles.  Tile t's and tile t + 1's item windows of a
+// range are adjacent, so the line they share is then completed in one L2
+// instead of being written partly from two (and the per-tile counts and
+// maxima of a range, adjacent words, likewise).  A bijection for any count.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
+  const int64_t q = ntiles / 8, r = ntiles % 8, x = b % 8, j = b / 8;
+  return x * q + (x < r ? x : r) + j;
+}
+
 template <bool CSR>
 __global__ __launch_bounds__(kCntThreads) void bin_count_kernel(BinArgs a) {
-  count_tile<CSR>(a, blockIdx.x);
+  count_tile<CSR>(a, xcd_tile(blockIdx.x, a.ntiles));
 }
 
 // ------------------------------------------------------------------ scan
@@ -836,7 +848,7 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
 
 // four workgroups per CU (the LDS target's occupancy): at most 128 VGPRs
 __global__ __launch_bounds__(kSThreads, 4) void bin_scatter_csr_kernel(BinArgs a) {
-  scatter_csr_tile(a, blockIdx.x);
+  scatter_csr_tile(a, xcd_tile(blockIdx.x, a.ntiles));
 }
 
 // Dense.  A round is 1024 rows, four per lane, one item per row (rounds
@@ -881,7 +893,7 @@ __device__ __forceinline__ void scatter_dense_tile(const BinArgs& a, int64_t til
 }
 
 __global__ __launch_bounds__(kSThreads) void bin_scatter_dense_kernel(BinArgs a) {
-  scatter_dense_tile(a, blockIdx.x);
+  scatter_dense_tile(a, xcd_tile(blockIdx.x, a.ntiles));
 }
 
 // ------------------------------------------------------------------ reduce
