@@ -109,6 +109,25 @@ class HipEvents:
             self.rt.hipEventDestroy(ctypes.c_void_p(h))
 
 
+def graph_steps(plan, steps, warmup):
+    """ms per step when the step is captured once in a HIP graph and
+    replayed (SketchPlan.capture): the same kernels, one launch per step.
+    Timed like pass 1 of timed_steps (host clock around synchronised
+    replays)."""
+    import torch
+    graph = plan.capture()
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    del graph
+    return ms
+
+
 def timed_steps(plan, steps, warmup, ev):
     """Run warmup steps, then three timed passes of `steps` steps each:
       1. no stage events: wall ms/step (every recorded event leaves the GPU
@@ -785,6 +804,8 @@ def main():
     achieved = sx_bytes / sx_s / 1e9
     traffic = counters_traffic(sx_bytes)
     gsx_flops = 2.0 * w.m * w.B * c.d
+    graph_ms = graph_steps(plan, args.steps, args.warmup)
+    log(f"the same step replayed from a HIP graph: {graph_ms:.4f} ms/step")
     log(f"wall {wall:.4f} ms/step; S X stage {sx_stage*1e3:.1f} us; "
         f"with all stage events: sx prologue {stage['sx_prologue']*1e3:.1f} us, "
         f"sx {stage['sx']*1e3:.1f} us, gsx {stage['gsx']*1e3:.1f} us, "
@@ -818,6 +839,8 @@ def main():
         # per-stage breakdown from a pass with an event at every stage
         # boundary (each stage then carries one event's idle time)
         "stages_us": {k: round(v * 1e3, 2) for k, v in stage.items()},
+        # the same step replayed from a HIP graph (one launch per step)
+        "graph": {"ms_per_step": round(graph_ms, 5), "nnz_per_s": nnz / (graph_ms * 1e-3)},
         "gsx": {"avg_launch_us": round(stage["gsx"] * 1e3, 2),
                 "tflops": round(gsx_flops / (stage["gsx"] * 1e-3) / 1e12, 3),
                 "frac_fp32_mfma_peak": round(gsx_flops / (stage["gsx"] * 1e-3) / 1e12

@@ -487,6 +487,21 @@ class SketchPlan:
             L.check(st, "cg_sketch_dense")
         return self.Y
 
+    def capture(self):
+        """A HIP graph of one run(): its kernels, recorded once on a side
+        stream (no stage events, which are host-side records).  Replaying it
+        (graph.replay()) recomputes Y from the current contents of X, with
+        one launch for the whole forward call.  The forward path issues no
+        memset or copy, so the graph holds kernel nodes only."""
+        if self._events is not None:
+            raise RuntimeError("stage events cannot be recorded into a graph")
+        self.run()                      # warm: first-use attributes set outside capture
+        torch.cuda.synchronize(self.device)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.run()
+        return graph
+
 
 # ---------------------------------------------------------------- batched
 class BatchedSketch:
