@@ -84,6 +84,7 @@ constexpr size_t kScatterLdsCsr = 40 * 1024;
 constexpr size_t kScatterLdsDense = 26 * 1024;
 constexpr int kMinStage = 1024;                // smallest output stage (items)
 constexpr int kSparseRound = 512;              // CSR rounds with at most this many entries skip the stage
+constexpr int kWalkLen = 2;                    // sparse rounds: rows up to this long are walked by their lane
 constexpr int kDenseCap = 8192;                // items sorted per dense reduce pass
 constexpr int kCsrMaxCells = 8192;             // cells of a CSR range's S X slice (64 KB of int64)
 constexpr int kDenseMaxBlocks = 128;           // 128-bucket blocks of a dense range (16384 / 128)
@@ -372,8 +373,7 @@ struct ScatterLds {
   uint32_t *g_base, *g_run, *r_cnt, *r_off, *r_fill, *r_max;   // R each
   uint2* fl;        // R: (window slot of stage index 0, window end)
   uint32_t* s_w;    // kSWaves
-  int32_t* s_seg;   // 8: (pad), last lane's end, (pad, pad), then per round parity
-                    // (round start, end from row_ptr)
+  int32_t* s_seg;   // 8 words: [1] the round's end as the last lane finds it (the rest unused)
 };
 
 __host__ __device__ inline size_t scatter_shared_bytes(bool csr) {
@@ -585,45 +585,91 @@ __device__ __forceinline__ void scatter_csr_tile(const BinArgs& a, int64_t tile)
   // before, and its first chunk of entries is requested before the count
   // and offset scans, so neither load's latency is waited out on its own.
   RpLoad<kRPT> rl_next = load_row_ptr<kRPT>(row_ptr, t0 + (int64_t)kWaveRows * wave, t1, vec);
-  // thread 0 also carries the next round's end, row_ptr[round end]
-  int32_t end_next = 0;
-  if (threadIdx.x == 0) end_next = row_ptr[min(t0 + kRoundRows, t1)];
+  // Every wavefront carries the round's bounds itself -- row_ptr at the
+  // round's first row, and at its end, loaded a round ahead (uniform loads)
+  // -- so all of them take the same sparse-or-not decision without LDS.
+  int32_t start_raw = row_ptr[t0];
+  int32_t end_next = row_ptr[min(t0 + kRoundRows, t1)];
+  // the first round waits for load_windows' state and the marks
+  bool after_dense = true;
   for (int64_t round = t0; round < t1; round += kRoundRows) {
     const int64_t r0 = round + (int64_t)kWaveRows * wave;
     const RpLoad<kRPT> rl = rl_next;
     rl_next = load_row_ptr<kRPT>(row_ptr, r0 + kRoundRows, t1, vec);   // clamped to t1 at the end
     const int32_t end_raw = end_next;
-    if (threadIdx.x == 0) end_next = row_ptr[min(round + 2 * kRoundRows, t1)];
+    end_next = row_ptr[min(round + 2 * kRoundRows, t1)];
     uint32_t hv[kRPT];
     lane_hashes<kRPT>(r0 + kRPT * lane, t1, row_offset, B, key, hv);
-    // the round's first entry (thread 0's first row start, as
-    // transpose_row_ptr clamps it) and its end (as the last lane finds it,
-    // for well-formed row_ptr), in the slots of the round's parity: after
-    // a sparse round a wavefront may write the next round's bounds before
-    // another has read this round's
-    const int sb = 4 + 2 * (int)(((round - t0) / kRoundRows) & 1);
-    if (threadIdx.x == 0) {
-      const int32_t s0 = min(max(rl.v[0], 0), nnz);
-      L.s_seg[sb] = s0;
-      L.s_seg[sb + 1] = max(min(max(end_raw, 0), nnz), s0);
-    }
-    __syncthreads();   // the previous round's flush is done with the LDS state
-    const int32_t S0 = __builtin_amdgcn_readfirstlane(L.s_seg[sb]);
-    const int32_t S1e = __builtin_amdgcn_readfirstlane(L.s_seg[sb + 1]);
-    if (S1e - S0 <= kSparseRound) {
-      // A sparse round: no counts, scans, stage or flush, and no barrier
-      // beyond the one above.  Each lane reserves its rows' slots with one
-      // LDS atomic per nonempty row and keeps a record per row (packed
-      // hash, slot of entry 0) in its wavefront's part of the stage, and
-      // its row starts in its wavefront's row_ptr window.  The wavefront's
-      // entries -- one contiguous segment -- are then taken 64 at a time;
-      // each finds its row by binary search over the starts and is stored
-      // straight to its window.  The order of items inside a range does
-      // not change the fixed-point sums.  Only wavefront-private LDS is
-      // written besides the range cursors and maxima (atomics), and the
-      // next round's barrier orders those.
+    // the round's first entry (as transpose_row_ptr clamps the first row
+    // start) and its end (as the last lane finds it, for well-formed row_ptr)
+    const int32_t S0 = min(max(start_raw, 0), nnz);
+    const int32_t S1e = max(min(max(end_raw, 0), nnz), S0);
+    start_raw = end_raw;
+    const bool sparse = S1e - S0 <= kSparseRound;
+    // Sparse rounds share nothing in LDS between wavefronts but the range
+    // cursors and maxima (atomics), so a wavefront goes from one to the next
+    // without waiting; a dense round, and the round after one, waits until
+    // every wavefront is done with the LDS state before it.
+    if (!sparse || after_dense) __syncthreads();
+    after_dense = !sparse;
+    if (sparse) {
+      // A sparse round: no counts, scans, stage or flush.  Each lane
+      // reserves its rows' slots with one LDS atomic per nonempty row, and
+      // every entry is stored straight to its range's window.  The order of
+      // items inside a range does not change the fixed-point sums.  Only
+      // wavefront-private LDS is written besides the range cursors and
+      // maxima (atomics); the barrier after the tile's last round orders
+      // those before the maxima are written out.
       int32_t rp[kRPT + 1];
       transpose_row_ptr<kRPT>(rl, w, nnz, rp);
+      int32_t lmax = 0;
+#pragma unroll
+      for (int j = 0; j < kRPT; ++j) lmax = max(lmax, rp[j + 1] - rp[j]);
+      if (__builtin_amdgcn_readlane(wave_incl_max(lmax), 63) <= kWalkLen) {
+        // Short rows only: each lane takes its own rows' entries (at most
+        // kWalkLen per row), all loads issued before the slot reservations.
+        int32_t cc[kRPT][kWalkLen];
+        float vv[kRPT][kWalkLen];
+#pragma unroll
+        for (int j = 0; j < kRPT; ++j)
+#pragma unroll
+          for (int e = 0; e < kWalkLen; ++e) {
+            cc[j][e] = 0;
+            vv[j][e] = 0.0f;
+            if (rp[j] + e < rp[j + 1]) {
+              cc[j][e] = col_idx[rp[j] + e];
+              vv[j][e] = vals[rp[j] + e];
+            }
+          }
+#pragma unroll
+        for (int j = 0; j < kRPT; ++j) {
+          const uint32_t len = (uint32_t)(rp[j + 1] - rp[j]);
+          if (!len) continue;
+          const uint32_t bucket = hash_bucket(hv[j]);
+          const uint32_t pr = bucket >> bp_shift;
+          const uint32_t s0 = L.g_base[pr] + atomicAdd(&L.g_run[pr], len);
+          const uint32_t wend = L.fl[pr].y;
+          const bool neg = hash_negative(hv[j]);
+          uint32_t mb = 0u;
+#pragma unroll
+          for (int e = 0; e < kWalkLen; ++e) {
+            if ((uint32_t)e < len) {
+              const bool ok = (uint32_t)cc[j][e] < (uint32_t)d;
+              const uint32_t cell = ok ? (bucket & bmask) * (uint32_t)d + (uint32_t)cc[j][e] : 0u;
+              const float sv = ok ? (neg ? -vv[j][e] : vv[j][e]) : 0.0f;
+              mb = max(mb, __float_as_uint(fabsf(sv)));
+              if (s0 + e < wend) items[s0 + e] = make_uint2(cell, __float_as_uint(sv));
+            }
+          }
+          atomicMax(&L.r_max[pr], mb);
+        }
+        continue;
+      }
+      // Longer rows: a record per row (packed hash, slot of entry 0) in the
+      // wavefront's part of the stage and the row starts in its row_ptr
+      // window; the wavefront's entries -- one contiguous segment -- are
+      // taken 64 at a time, each finding its row by binary search over the
+      // starts, so a long row is spread over the lanes.
       uint2* rec = L.stage + wave * kWaveRows;
 #pragma unroll
       for (int j = 0; j < kRPT; ++j) {

@@ -247,6 +247,41 @@ def test_binned_csr_sparse_and_dense_rounds(cuda, d, long_rows):
     assert rel(Y.cpu().numpy(), O.sketch_csr(rp, ci, v, n, d, m, B, seed)) < TOL[torch.float32]
 
 
+@pytest.mark.parametrize("aligned", [True, False])
+def test_binned_csr_sparse_rounds_short_rows(cuda, aligned):
+    """Sparse rounds whose rows hold 0 to 3 entries: a wavefront whose rows
+    all hold at most two entries lets each lane take its own rows' entries,
+    one with a 3-entry row spreads the entries over the lanes instead; both
+    kinds, and row_ptr with and without 16-byte alignment (the row starts
+    then go through LDS), must give the oracle's S X bit-identically."""
+    rng = np.random.default_rng(57)
+    n, d, m, B, seed = 70000, 16, 20, 30000, 9
+    # about 0.4 entries per row: rows of length 0, 1, 2, and 3 in about one
+    # wavefront in two (256 rows of 1 in 300 chance each)
+    lens = rng.choice([0, 1, 2, 3], size=n, p=[0.7, 0.2, 0.097, 0.003])
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col_idx = np.concatenate([np.sort(rng.choice(d, size=k, replace=False)) for k in lens]).astype(np.int32)
+    vals = rng.standard_normal(col_idx.size).astype(np.float32)
+    rp_t = torch.from_numpy(row_ptr).to(cuda)
+    if not aligned:
+        # the same values at a 4-byte offset from a 16-byte boundary
+        buf = torch.empty(n + 2, dtype=torch.int32, device=cuda)
+        buf[1:].copy_(rp_t)
+        rp_t = buf[1:]
+        assert rp_t.data_ptr() % 16 != 0
+    X = cg.CsrMatrix(rp_t, torch.from_numpy(col_idx).to(cuda), torch.from_numpy(vals).to(cuda), n, d)
+    say("binned sparse rounds, short rows", aligned, len(col_idx))
+    sxs = []
+    for _ in range(3):
+        SX = torch.empty((B, d), dtype=torch.float32, device=cuda)
+        Y = cg.sketch(X, m, B, seed, algo="binned", sx_out=SX)
+        sxs.append(SX)
+    torch.cuda.synchronize()
+    assert torch.equal(sxs[0], sxs[1]) and torch.equal(sxs[0], sxs[2])
+    assert rel(sxs[0].cpu().numpy(), O.sx_csr(row_ptr, col_idx, vals, n, d, seed, B)) < SXTOL[torch.float32]
+    assert rel(Y.cpu().numpy(), O.sketch_csr(row_ptr, col_idx, vals, n, d, m, B, seed)) < TOL[torch.float32]
+
+
 @pytest.mark.parametrize("algo", ["atomic", "binned", "sorted"])
 def test_nan_and_inf_reach_their_bucket(cuda, algo):
     rng = np.random.default_rng(13)
