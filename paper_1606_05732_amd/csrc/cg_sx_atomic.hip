@@ -113,27 +113,48 @@ __global__ __launch_bounds__(kThreads) void sx_dense_atomic_kernel(
   }
 }
 
-// Dense X, any d <= kMaxD: the whole wave walks one row at a time.
+// Dense X, d > 64: workgroup (bx, by) takes columns [64 by, 64 by + 64), a
+// lane per column, and each of its wavefronts a run of rpw rows (at most
+// kRowsPerWave, a multiple of 4), U rows in flight before their atomics.
+// A row's 64 columns are one coalesced load and 64 atomics on adjacent
+// words of its S X row.  rpw shrinks for small X, so that a 1000-row X
+// still spreads over some thousand wavefronts.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void sx_dense_wide_kernel(
     const T* __restrict__ X, int64_t ldx, int64_t n, int d, uint32_t B, Key key,
-    uint64_t row_offset, T* __restrict__ SX) {
+    uint64_t row_offset, T* __restrict__ SX, int rpw) {
+  constexpr int U = 8;
   __shared__ uint32_t s_hash[kWaves][kRowsPerWave];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t r0 = ((int64_t)blockIdx.x * kWaves + wave) * kRowsPerWave;
-  const int nr = r0 < n ? (int)min((int64_t)kRowsPerWave, n - r0) : 0;
+  const int64_t r0 = ((int64_t)blockIdx.x * kWaves + wave) * rpw;
+  const int nr = r0 < n ? (int)min((int64_t)rpw, n - r0) : 0;
   uint32_t* sh = s_hash[wave];
   if (nr > 0) hash_rows_to_lds(sh, row_offset + (uint64_t)r0, nr, B, key, lane);
   __syncthreads();
-  for (int j = 0; j < nr; ++j) {
-    const uint32_t hp = sh[j];
-    T* dst = SX + (size_t)hash_bucket(hp) * d;
-    const T* src = X + (r0 + j) * ldx;
-    for (int c = lane; c < d; c += 64) {
-      const T v = src[c];
-      atomic_add(&dst[c], hash_negative(hp) ? -v : v);
+  const int c = (int)blockIdx.y * 64 + lane;
+  if (nr == 0 || c >= d) return;
+  const T* xc = X + r0 * ldx + c;
+  for (int j0 = 0; j0 < nr; j0 += U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = j0 + u < nr ? xc[(int64_t)(j0 + u) * ldx] : T(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j0 + u < nr) {
+        const uint32_t hp = sh[j0 + u];
+        atomic_add(&SX[(size_t)hash_bucket(hp) * d + c], hash_negative(hp) ? -v[u] : v[u]);
+      }
     }
   }
+}
+
+// Rows per wavefront of the wide kernel: about 4096 wavefronts over the
+// whole product (rows x 64-column groups), 4 to kRowsPerWave rows each.
+inline int wide_rows_per_wave(int64_t n, int d) {
+  const int64_t groups = (d + 63) / 64;
+  int64_t r = (n * groups + 4095) / 4096;
+  r = (r + 3) / 4 * 4;
+  return (int)(r < 4 ? 4 : r > kRowsPerWave ? kRowsPerWave : r);
 }
 
 inline unsigned blocks_for_rows(int64_t n) {
@@ -173,8 +194,12 @@ hipError_t launch_sx_dense_atomic(const T* X, int64_t ldx, int64_t n, int d, uin
     sx_dense_atomic_kernel<T, 32><<<g, kThreads, 0, s>>>(X, ldx, n, d, B, key, row_offset, SX);
   else if (d <= 64)
     sx_dense_atomic_kernel<T, 64><<<g, kThreads, 0, s>>>(X, ldx, n, d, B, key, row_offset, SX);
-  else
-    sx_dense_wide_kernel<T><<<g, kThreads, 0, s>>>(X, ldx, n, d, B, key, row_offset, SX);
+  else {
+    const int rpw = wide_rows_per_wave(n, d);
+    const int64_t per = (int64_t)kWaves * rpw;
+    const dim3 grid((unsigned)((n + per - 1) / per), (unsigned)((d + 63) / 64));
+    sx_dense_wide_kernel<T><<<grid, kThreads, 0, s>>>(X, ldx, n, d, B, key, row_offset, SX, rpw);
+  }
   return hipGetLastError();
 }
 

@@ -202,6 +202,23 @@ def test_binned_csr_is_bitwise_reproducible(cuda, kind):
     assert rel(sxs[0].cpu().numpy(), O.sx_csr(rp, ci, v, n, d, seed, B)) < 2e-7
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_dense_wide_atomic_many_rows(cuda, dtype):
+    """Dense X wider than 64 columns on the atomic path: 64-column groups
+    along the grid's second dimension and, for this n, about a hundred rows
+    per wavefront (a ragged last run); S X and Y against the oracle."""
+    n, d, m, B = 150001, 130, 16, 2500
+    X = _dense_case(n, d, 77, dtype)
+    seed = 4321
+    say("dense wide atomic", dtype, n, d)
+    Xg = torch.from_numpy(X).to(cuda)
+    SX = torch.empty((B, d), dtype=dtype, device=cuda)
+    Y = cg.sketch(Xg, m, B, seed, algo="atomic", sx_out=SX)
+    torch.cuda.synchronize()
+    assert rel(SX.cpu().numpy(), O.sx_dense(X.astype(np.float64), seed, B)) < SXTOL[dtype]
+    assert rel(Y.cpu().numpy(), O.sketch_dense(X.astype(np.float64), m, B, seed)) < TOL[dtype]
+
+
 def _mixed_density_csr(rng, n, d, block, dense_p, sparse_p, long_rows):
     """CSR whose 1024-row blocks alternate between dense_p and sparse_p
     density, plus the given rows made (almost) full: rounds of both kinds
