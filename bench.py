@@ -279,7 +279,7 @@ def normals_ceiling(m, B, seed, reps=20):
     return ms * 1e3
 
 
-def ladder(steps, warmup, ev):
+def ladder(steps, warmup, ev, read_gbs):
     import numpy as np  # noqa: F401
     import torch
 
@@ -297,6 +297,9 @@ def ladder(steps, warmup, ev):
     out["rng_bound_us"] = round(rng_us, 2)
     out["rng_normals_per_s"] = float(f"{w.m * w.B / (rng_us * 1e-6):.4g}")
     log(f"ladder: drawing the {w.m} x {w.B} normals alone takes {rng_us:.1f} us")
+    # every rung reads the FP32 S X once, at best at the measured read rate
+    sx_read_us = 4.0 * w.B * w.d / (read_gbs * 1e9) * 1e6
+    out["sx_read_bound_us"] = round(sx_read_us, 2)
     for prec in ("native", "bf16", "fp8"):
         plan = cg.SketchPlan(X, w.m, w.B, w.seed, precision=prec)
         wall, stage, total, _ = timed_steps(plan, steps, warmup, ev)
@@ -312,6 +315,16 @@ def ladder(steps, warmup, ev):
             "frac_of_mfma_peak": round(tflops / MFMA_PEAK_TFLOPS[rung], 4),
             "frac_of_rng_bound": round(rng_us / (stage["gsx"] * 1e3), 3),
             "rel_fro_err_vs_fp64": float(f"{err:.3e}")}
+        # the rung's floor: the longest of its S X read, its normals and its
+        # MFMA time at the dtype's peak -- for FP32 the normals plus the
+        # MFMA time, since FP32 MFMAs and the generator's VALU work do not
+        # run concurrently on this part, even in different wavefronts of a
+        # SIMD
+        mfma_us = flops / (MFMA_PEAK_TFLOPS[rung] * 1e12) * 1e6
+        gen_us = rng_us + mfma_us if rung == "fp32" else max(rng_us, mfma_us)
+        floor_us = max(sx_read_us, gen_us)
+        out[rung]["floor_us"] = round(floor_us, 2)
+        out[rung]["frac_of_floor"] = round(floor_us / (stage["gsx"] * 1e3), 3)
         log(f"ladder {prec}: {wall:.3f} ms/step, gsx {stage['gsx']*1e3:.1f} us "
             f"({rng_us / (stage['gsx'] * 1e3):.2f} of the generator's ceiling), err {err:.2e}")
         del plan
@@ -864,7 +877,7 @@ def main():
     if not args.no_other_configs:
         result["other_configs"] = other_configs(max(5, args.steps // 2), 2, ev)
     if not args.no_ladder:
-        result["ladder"] = ladder(max(5, args.steps // 2), 2, ev)
+        result["ladder"] = ladder(max(5, args.steps // 2), 2, ev, ceil["read_gbs"])
     if not args.no_batched:
         result["batched"] = batched(log)
     if not args.no_adjoint:

@@ -426,7 +426,7 @@ int cg_debug_stream(int kind, const void* src, void* dst, int64_t bytes,
  * of CG_NORMALS_SINK threads writes the sum of its normals to sink[t].
  * m: a positive multiple of 4 up to 2^24; 1 <= B < 2^31.  sink: device
  * float[CG_NORMALS_SINK].  stream: hipStream_t.                           */
-#define CG_NORMALS_SINK (1 << 21)
+#define CG_NORMALS_SINK (1 << 19)
 int cg_debug_normals(uint64_t seed, int64_t m, int64_t B, float* sink,
                      void* stream);
 

@@ -19,7 +19,7 @@ CG_PROJ_COUNTGAUSS, CG_PROJ_GAUSSIAN = 0, 1
 CG_KIND_LEMMA = 8
 CG_STREAM_COPY, CG_STREAM_READ, CG_STREAM_WRITE = 0, 1, 2
 CG_STREAM_COPY_NT, CG_STREAM_READ_NT, CG_STREAM_WRITE_NT = 3, 4, 5
-CG_NORMALS_SINK = 1 << 21
+CG_NORMALS_SINK = 1 << 19
 
 # Every function declared in include/countgauss.h.
 EXPORTS = [

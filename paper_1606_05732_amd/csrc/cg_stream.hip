@@ -85,28 +85,49 @@ __global__ __launch_bounds__(kThreads) void stream_write_kernel(u32x4* __restric
 // row quads [0, m / 4) (Philox4x32-10 of counter (b, q, 1, 0), FP32
 // Box-Muller, exactly as the contractions draw them), with nothing else:
 // each thread adds up its normals and writes one sum.  Thread t takes the
-// blocks t, t + T, ... (T threads), eight in flight.
+// contiguous run of blocks [t per, (t + 1) per) in (b, q) order, with the
+// counters stepped by increments (one division per thread, none per
+// block), eight blocks in flight.
 __global__ __launch_bounds__(kThreads) void normals_rate_kernel(Key key, uint32_t quads, int64_t B,
+                                                                int64_t per,
                                                                 float* __restrict__ sink) {
-  const int64_t T = (int64_t)gridDim.x * kThreads;
   const int64_t t0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t nblk = B * quads;
   constexpr int U = 8;
   float acc = 0.0f;
-  int64_t i = t0;
-  for (; i + (U - 1) * T < nblk; i += U * T) {
+  int64_t k = t0 * per;
+  const int64_t kend = min(k + per, nblk);
+  uint32_t b = 0u, q = 0u;
+  if (k < kend) {
+    b = (uint32_t)(k / quads);
+    q = (uint32_t)(k % quads);
+  }
+  for (; k + U <= kend; k += U) {
+    uint32_t bb[U], qq[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t k = i + u * T;
+      bb[u] = b;
+      qq[u] = q;
+      if (++q == quads) {
+        q = 0u;
+        ++b;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
       float z[4];
-      box_muller(gauss_block((uint32_t)(k / quads), (uint32_t)(k % quads), key.k0, key.k1), z);
+      box_muller(gauss_block(bb[u], qq[u], key.k0, key.k1), z);
       acc += (z[0] + z[1]) + (z[2] + z[3]);
     }
   }
-  for (; i < nblk; i += T) {
+  for (; k < kend; ++k) {
     float z[4];
-    box_muller(gauss_block((uint32_t)(i / quads), (uint32_t)(i % quads), key.k0, key.k1), z);
+    box_muller(gauss_block(b, q, key.k0, key.k1), z);
     acc += (z[0] + z[1]) + (z[2] + z[3]);
+    if (++q == quads) {
+      q = 0u;
+      ++b;
+    }
   }
   sink[t0] = acc;
 }
@@ -115,11 +136,16 @@ __global__ __launch_bounds__(kThreads) void normals_rate_kernel(Key key, uint32_
 
 int stream_blocks() { return 256 * 32; }
 
-int normals_threads() { return 256 * 32 * kThreads; }
+// 2048 workgroups: eight wavefronts per SIMD, each thread drawing a run
+// of blocks long enough that the launch's own ramp does not dominate
+constexpr int kNormalsBlocks = 2048;
+int normals_threads() { return kNormalsBlocks * kThreads; }
 
 hipError_t launch_normals_rate(Key key, int64_t m, int64_t B, float* sink, hipStream_t s) {
-  normals_rate_kernel<<<(unsigned)stream_blocks(), kThreads, 0, s>>>(key, (uint32_t)(m / 4), B,
-                                                                     sink);
+  const int64_t T = (int64_t)normals_threads();
+  const int64_t per = (B * (m / 4) + T - 1) / T;
+  normals_rate_kernel<<<(unsigned)kNormalsBlocks, kThreads, 0, s>>>(key, (uint32_t)(m / 4), B, per,
+                                                                    sink);
   return hipGetLastError();
 }
 
