@@ -315,15 +315,14 @@ def ladder(steps, warmup, ev, read_gbs):
             "frac_of_mfma_peak": round(tflops / MFMA_PEAK_TFLOPS[rung], 4),
             "frac_of_rng_bound": round(rng_us / (stage["gsx"] * 1e3), 3),
             "rel_fro_err_vs_fp64": float(f"{err:.3e}")}
-        # the rung's floor: the longest of its S X read, its normals and its
-        # MFMA time at the dtype's peak.  A wavefront that both draws and
-        # multiplies (this kernel's structure) barely overlaps the two, so
-        # the normals plus the MFMA time are reported beside it
+        # the rung's floor: its S X read, or its normals plus its MFMA time
+        # at the dtype's peak (added: a SIMD never issues vector ALU and
+        # MFMA instructions in the same cycle on this part -- the
+        # co-execution counter stays at zero), whichever is longer
         mfma_us = flops / (MFMA_PEAK_TFLOPS[rung] * 1e12) * 1e6
-        floor_us = max(sx_read_us, rng_us, mfma_us)
+        floor_us = max(sx_read_us, rng_us + mfma_us)
         out[rung]["floor_us"] = round(floor_us, 2)
         out[rung]["frac_of_floor"] = round(floor_us / (stage["gsx"] * 1e3), 3)
-        out[rung]["normals_plus_mfma_us"] = round(rng_us + mfma_us, 2)
         log(f"ladder {prec}: {wall:.3f} ms/step, gsx {stage['gsx']*1e3:.1f} us "
             f"({rng_us / (stage['gsx'] * 1e3):.2f} of the generator's ceiling), err {err:.2e}")
         del plan

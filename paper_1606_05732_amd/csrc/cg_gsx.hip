@@ -83,7 +83,9 @@ __device__ __forceinline__ void block_reduce_store(V (&acc)[4][NB], T* red, int 
                                                    T* __restrict__ out) {
   constexpr int R = 16 * NB;   // accumulator values per lane
   constexpr int MB = PAIRS ? 2 : 4;
-  if (wave > 0) {
+  // wavefronts 0 .. 3 hold the accumulators (any others take part in the
+  // barrier only)
+  if (wave > 0 && wave < kWaves) {
 #pragma unroll
     for (int t = 0; t < MB; ++t)
 #pragma unroll
@@ -288,6 +290,117 @@ __global__ __launch_bounds__(kThreads, 4) void gsx_native_kernel(const T* __rest
   else
     gsx_native_block<T, NB, false, TAG>(SX, ld, col0, B, d, m, kc, key, part, blockIdx.x,
                                         blockIdx.y, blockIdx.z, red);
+}
+
+// Producer/consumer form of the FP32 contraction, for full row groups
+// (more than 32 rows of G): eight wavefronts per workgroup.  Wavefronts
+// 0-3 are consumers: each owns a chunk of kc columns of G as a wavefront of
+// gsx_native_block does, and only multiplies.  Wavefronts 4-7 are
+// producers: they draw the normals of all four chunks into LDS, kPcStage
+// columns per chunk at a time, double buffered one stage ahead.
+// Wavefronts w and w + 4 share a SIMD, so every SIMD has one wavefront on
+// the generator's vector work and one on FP32 MFMAs.  A SIMD issues only
+// one of the two kinds in any cycle, but each kind can now issue while the
+// other waits on its own dependencies.  A consumer lane (p, kq) reads, for its
+// K slot kq, the four normals of row quad 16 group + p as one 16-byte LDS
+// word, exactly the values a lane of gsx_native_block draws itself, and
+// multiplies them in the same order; the cross-wavefront sum is the same
+// too, so the partials are bit for bit those of gsx_native_block.
+constexpr int kPcStage = 16;                          // columns per chunk per stage
+constexpr int kPcStageFloats = kWaves * kPcStage * 64;   // chunks x columns x 16 quads x 4 rows
+
+template <int NB, int TAG>
+__global__ __launch_bounds__(2 * kThreads, 2) void gsx_pc_kernel(const float* __restrict__ SX,
+                                                               int64_t ld, uint64_t col0, int64_t B,
+                                                               int d, int m, int kc, Key key,
+                                                               float* __restrict__ part) {
+  constexpr int kLds = red_elems<float, NB>() > 2 * kPcStageFloats ? red_elems<float, NB>()
+                                                                   : 2 * kPcStageFloats;
+  __shared__ __align__(16) float lds[kLds];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int group = (int)blockIdx.y;
+  const int n0 = (int)blockIdx.z * NB * 16;
+  const int64_t bx = blockIdx.x;
+  const int nst = kc / kPcStage;   // kc is a multiple of 16 for FP32
+  v4f acc[4][NB];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
+  if (wave >= kWaves) {
+    // producer lane L: column j = L / 16 of the stage and quad 16 group +
+    // L % 16, for each of the four chunks
+    const int L = (wave - kWaves) * 64 + lane;
+    const int j = L >> 4, pq = L & 15;
+    const uint32_t q = (uint32_t)(16 * group + pq);
+    auto produce = [&](int st, int buf) {
+#pragma unroll
+      for (int c = 0; c < kWaves; ++c) {
+        const int64_t b = (bx * kWaves + c) * kc + (int64_t)st * kPcStage + j;
+        float g[4];
+        box_muller(k_block<TAG>(b, col0, q, key), g);
+        *(v4f*)&lds[(((buf * kWaves + c) * kPcStage + j) * 16 + pq) * 4] = v4f{g[0], g[1], g[2], g[3]};
+      }
+    };
+    produce(0, 0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      if (st + 1 < nst) produce(st + 1, (st + 1) & 1);
+      __syncthreads();   // this stage consumed, the next one written
+    }
+  } else {
+    const int p = lane & 15, kq = lane >> 4;
+    const int64_t kbeg = (bx * kWaves + wave) * (int64_t)kc;
+    const int64_t kend = min(kbeg + (int64_t)kc, B);
+    int col[NB], ccol[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      col[nb] = n0 + nb * 16 + p;
+      ccol[nb] = min(col[nb], d - 1);
+    }
+    // S X of a stage (its four K steps), loaded a stage ahead at indices
+    // clamped onto the chunk's last row; rows past the chunk (or past B,
+    // for a chunk that starts there) are zeroed when used
+    const int64_t clast = (kend > kbeg ? kend : B) - 1;
+    auto load_stage = [&](int st, float (&x)[4][NB]) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t b = kbeg + (int64_t)st * kPcStage + 4 * k + kq;
+        const int64_t cb = b < clast ? b : clast;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) x[k][nb] = SX[cb * ld + ccol[nb]];
+      }
+    };
+    float xn[4][NB];
+    load_stage(0, xn);
+    __syncthreads();   // stage 0 written
+    for (int st = 0; st < nst; ++st) {
+      float x[4][NB];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) x[k][nb] = xn[k][nb];
+      if (st + 1 < nst) load_stage(st + 1, xn);
+      const float* stage = lds + ((st & 1) * kWaves + wave) * kPcStage * 64;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const v4f g = *(const v4f*)&stage[((4 * k + kq) * 16 + p) * 4];
+        const bool bok = kbeg + (int64_t)st * kPcStage + 4 * k + kq < kend;
+        float xv[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) xv[nb] = bok && col[nb] < d ? x[k][nb] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma_k4(g[t], xv[nb], acc[t][nb]);
+      }
+      __syncthreads();   // this stage consumed, the next one written
+    }
+  }
+  // every stage read before the cross-wavefront sum reuses the LDS (the
+  // loop's last barrier)
+  block_reduce_store<float, NB, v4f, false, false>(acc, lds, wave, lane, group, n0, m, d,
+                                                   part + (size_t)bx * m * d);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -876,6 +989,15 @@ template <typename T, int NB, int TAG = 1>
 void launch_native(const GsxPlan& pl, const T* SX, int64_t B, int d, int m, Key key, T* part,
                    hipStream_t s, int64_t ld = -1, uint64_t col0 = 0) {
   dim3 grid((unsigned)pl.parts, (unsigned)pl.mgroups, (unsigned)pl.ngroups);
+  // FP32 with every row group full (no group of 32 rows or fewer): the
+  // producer/consumer form; same partials
+  if constexpr (sizeof(T) == 4) {
+    if (m % 64 == 0 || m % 64 > 32) {
+      gsx_pc_kernel<NB, TAG><<<grid, 2 * kThreads, 0, s>>>(SX, ld < 0 ? (int64_t)d : ld, col0, B, d,
+                                                            m, pl.kc, key, part);
+      return;
+    }
+  }
   gsx_native_kernel<T, NB, TAG><<<grid, kThreads, 0, s>>>(SX, ld < 0 ? (int64_t)d : ld, col0, B, d,
                                                            m, pl.kc, key, part);
 }
