@@ -70,6 +70,37 @@ def test_csr_adjoint_parity_and_identity(cuda, dtype):
     assert abs(lhs - rhs) <= 10 * TOL[dtype] * (abs(lhs) + 1)
 
 
+@pytest.mark.parametrize("case", ["long_rows", "mixed", "sparse_offset"])
+def test_csr_adjoint_row_shapes(cuda, case):
+    """The CSR gather on rows of about 100 entries (a row spans several of
+    a wavefront's 64-entry windows), on short rows with a few long ones, and
+    on very sparse rows (mostly empty) with a row offset, against the
+    oracle's FP64 adjoint."""
+    rng = np.random.default_rng(23)
+    row_offset = 0
+    if case == "long_rows":
+        n, d, m, B, seed = 3001, 200, 24, 700, 8
+        rp, ci, v = W.csr_bernoulli(rng, n, d, 0.5, dtype=np.float32)
+    elif case == "mixed":
+        n, d, m, B, seed = 9000, 160, 20, 1500, 9
+        mask = rng.random((n, d)) < 0.02
+        mask[rng.choice(n, 12, replace=False)] = rng.random((12, d)) < 0.9
+        rp = np.concatenate([[0], np.cumsum(mask.sum(axis=1))]).astype(np.int32)
+        ci = np.nonzero(mask)[1].astype(np.int32)
+        v = rng.standard_normal(ci.size).astype(np.float32)
+    else:
+        n, d, m, B, seed = 20003, 16, 16, 4000, 10
+        rp, ci, v = W.csr_bernoulli(rng, n, d, 0.01, dtype=np.float32)
+        row_offset = 123457
+    dY = rng.standard_normal((m, d)).astype(np.float32)
+    say("adjoint csr row shapes", case, len(ci))
+    X = csr_to_gpu(rp, ci, v, n, d, cuda)
+    dv = cg.sketch_adjoint_csr(X, torch.from_numpy(dY).to(cuda), m, B, seed, row_offset=row_offset)
+    torch.cuda.synchronize()
+    ref = O.adjoint_csr(rp, ci, dY.astype(np.float64), n, d, m, B, seed, row_offset=row_offset)
+    assert rel(dv.cpu().numpy(), ref) < TOL[torch.float32]
+
+
 def test_finite_differences_on_slice(cuda):
     """X[0:4096, 0:8] of the gradient workload as its own input, m = 128,
     B = 2^19: the GPU adjoint equals the oracle's FP64 adjoint on every
