@@ -1052,7 +1052,10 @@ GsxPlan plan_gsx(int64_t m, int64_t B, int64_t d, Prec prec, int kc_request, siz
     const int64_t target = 2048;
     const int64_t units = (int64_t)pl.mgroups * pl.ngroups;
     kc = (B * units + target - 1) / target;
-    if (kc < 64) kc = 64;
+    // ... unless 64-column chunks leave fewer than 1024 wavefronts (a
+    // small B): then chunks down to the granule, for about 1024 of them, so
+    // that the wavefronts' chains of steps stay short
+    if (kc < 64) kc = (B * units + 63) / 64 >= 1024 ? 64 : (B * units + 1023) / 1024;
     if (kc > 8192) kc = 8192;
   }
   // at most 2^23 workgroups along B (a grid holds fewer than 2^32 work-items)
