@@ -684,6 +684,181 @@ __global__ __launch_bounds__(kThreads, FP8 ? 2 : 4) void gsx_lowp_kernel(const f
                                           part + (size_t)bx * m * d);
 }
 
+// Producer/consumer form of the reduced-precision contraction: eight
+// wavefronts per workgroup.  Wavefront c < 4 is a consumer with the chunk
+// of gsx_lowp_kernel's wavefront c: it loads and packs S X and multiplies.
+// Wavefront c + 4 is its producer: its lane l draws and packs, a 32-column
+// step ahead, exactly the G operand consumer lane l would draw (eight
+// Philox blocks, Box-Muller, BF16 pairs or FP8 bytes), into a double-
+// buffered LDS slot of that lane.  The producers never wait on memory, so
+// the consumers' S X loads wait behind their work.  Same operands, same
+// MFMA order, same accumulation and cross-wavefront sum as
+// gsx_lowp_kernel: the partials are bit for bit its partials.  Every
+// consumer runs all kc / 32 steps of its chunk (steps past its end, which
+// only the last chunk has, multiply zeroed S X), so that the eight
+// wavefronts meet at the same barriers.
+template <int NB, bool FP8, bool VEC>
+__global__ __launch_bounds__(2 * kThreads) void gsx_lowp_pc_kernel(
+    const float* __restrict__ SX, int64_t row0, int64_t bx0, int64_t B, int d, int m, int kc,
+    Key key, const float2* __restrict__ bscale, float* __restrict__ part) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  constexpr int KBLK = FP8 ? 128 : 32;
+  constexpr int GW = FP8 ? 2 : 4;                        // G words per M block per step
+  constexpr int kSlot = 4 * GW;                          // words per lane per step
+  constexpr int kBuf = kWaves * 64 * kSlot;              // words per buffer
+  constexpr int kRed = 3 * 16 * NB * 64;
+  constexpr int kLds = kRed > 2 * kBuf ? kRed : 2 * kBuf;
+  __shared__ __align__(16) float lds[kLds];
+  uint32_t* gbuf = (uint32_t*)lds;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = lane & 15, kq = lane >> 4;
+  const int group = blockIdx.y;
+  const uint32_t q = (uint32_t)(16 * group + p);
+  const int n0 = blockIdx.z * NB * 16;
+  const int c = wave & (kWaves - 1);                      // the chunk this wavefront serves
+  const int64_t bx = bx0 + blockIdx.x;
+  const int64_t kbeg = (bx * kWaves + c) * kc;
+  const int64_t kend = min(kbeg + (int64_t)kc, B);
+  const int nsteps = kc / 32;                             // kc: a multiple of KBLK
+  v4f acc[4][NB];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
+  if (wave >= kWaves) {
+    uint32_t* slot = gbuf + (c * 64 + lane) * kSlot;
+    auto produce = [&](int st, int buf) {
+      const int64_t base = kbeg + 32 * (int64_t)st + kq * 8;
+      uint32_t gw[4][GW];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        float z0[4], z1[4];
+        box_muller(gauss_block((uint32_t)(base + e), q, key.k0, key.k1), z0, FP8 ? 64.0f : 1.0f);
+        box_muller(gauss_block((uint32_t)(base + e + 1), q, key.k0, key.k1), z1, FP8 ? 64.0f : 1.0f);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if constexpr (FP8) {
+            uint32_t& w = gw[t][e >> 2];
+            w = (e & 2) ? (uint32_t)cvt_fp8<true>(z0[t], z1[t], (int)w)
+                        : (uint32_t)cvt_fp8<false>(z0[t], z1[t], 0);
+          } else {
+            gw[t][e >> 1] = bf16_pair(z0[t], z1[t]);
+          }
+        }
+      }
+      uint32_t* dst = slot + buf * kBuf;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if constexpr (FP8) {
+          *(uint2*)(dst + t * GW) = make_uint2(gw[t][0], gw[t][1]);
+        } else {
+          *(u32x4*)(dst + t * GW) = u32x4{gw[t][0], gw[t][1], gw[t][2], gw[t][3]};
+        }
+      }
+    };
+    produce(0, 0);
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+      if (st + 1 < nsteps) produce(st + 1, (st + 1) & 1);
+      __syncthreads();   // this step consumed, the next one written
+    }
+  } else {
+    bool cok[NB];
+    uint32_t ccol[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int col = VEC ? n0 + NB * p + nb : n0 + 16 * nb + p;
+      cok[nb] = col < d;
+      ccol[nb] = 4u * (uint32_t)min(col, d - 1);   // bytes
+    }
+    const uint32_t ud = 4u * (uint32_t)d;
+    const uint32_t last = (uint32_t)((kend > kbeg ? kend : B) - 1 - row0) * ud;
+    uint32_t off = (uint32_t)(kbeg + kq * 8 - row0) * ud;
+    float xn[8][NB];
+    lowp_load_rows<NB, VEC>(SX, off, ud, last, ccol, xn);
+    const uint32_t* slot = gbuf + (c * 64 + lane) * kSlot;
+    const int64_t nblk = (B + 127) / 128;
+    float yscale = 1.0f, xscale = 1.0f;
+    v4f tmp[4][NB];
+    __syncthreads();   // step 0 written
+    for (int st = 0; st < nsteps; ++st) {
+      const int sub = st % (KBLK / 32);
+      const int64_t kb = kbeg + (int64_t)(st - sub) * 32;
+      if constexpr (FP8) {
+        if (sub == 0) {
+          const float2 sc = bscale[min(kb >> 7, nblk - 1)];
+          xscale = sc.x;
+          yscale = sc.y;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) tmp[t][nb] = v4f{0, 0, 0, 0};
+        }
+      }
+      const int64_t base = kb + sub * 32 + kq * 8;
+      if (kb + sub * 32 + 32 > kend) {   // the same in the whole wavefront
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) xn[e][nb] = base + e < kend ? xn[e][nb] : 0.0f;
+      }
+      uint32_t xw[NB][4];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+          float x0 = xn[e][nb], x1 = xn[e + 1][nb];
+          if constexpr (!VEC) {
+            x0 = cok[nb] ? x0 : 0.0f;
+            x1 = cok[nb] ? x1 : 0.0f;
+          }
+          if constexpr (FP8) {
+            uint32_t& w = xw[nb][e >> 2];
+            w = (e & 2) ? (uint32_t)cvt_fp8<true>(x0 * xscale, x1 * xscale, (int)w)
+                        : (uint32_t)cvt_fp8<false>(x0 * xscale, x1 * xscale, 0);
+          } else {
+            xw[nb][e >> 1] = bf16_pair(x0, x1);
+          }
+        }
+      }
+      off += 32 * ud;
+      lowp_load_rows<NB, VEC>(SX, off, ud, last, ccol, xn);
+      const uint32_t* src = slot + (st & 1) * kBuf;
+      if constexpr (FP8) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const uint2 g = *(const uint2*)(src + t * GW);
+          const long ga = (long)g.x | ((long)g.y << 32);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const long xa = (long)xw[nb][0] | ((long)xw[nb][1] << 32);
+            tmp[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ga, xa, tmp[t][nb], 0, 0, 0);
+          }
+        }
+        if (sub == KBLK / 32 - 1) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[t][nb] += tmp[t][nb] * yscale;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const v8bf gb = __builtin_bit_cast(v8bf, *(const u32x4*)(src + t * GW));
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const v8bf xb = __builtin_bit_cast(v8bf, u32x4{xw[nb][0], xw[nb][1], xw[nb][2], xw[nb][3]});
+            acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb, xb, acc[t][nb], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();   // this step consumed, the next one written
+    }
+  }
+  block_reduce_store<float, NB, v4f, VEC>(acc, lds, wave, lane, group, n0, m, d,
+                                          part + (size_t)bx * m * d);
+}
+
 // Y[o] = sum over partials p of part[p][o]: 16 wavefronts each add a
 // contiguous sixteenth of the partials (eight loads in flight), then the
 // sixteen sums are added in order.  Fixed order, so the result does not
@@ -1024,11 +1199,11 @@ void launch_lowp(const GsxPlan& pl, const float* SX, int64_t B, int d, int m, Ke
     const int64_t row0 = bx0 * rows_per_part;
     dim3 grid((unsigned)np, (unsigned)pl.mgroups, (unsigned)pl.ngroups);
     if (vec)
-      gsx_lowp_kernel<NB, FP8, (NB == 2 || NB == 4)><<<grid, kThreads, 0, s>>>(
+      gsx_lowp_pc_kernel<NB, FP8, (NB == 2 || NB == 4)><<<grid, 2 * kThreads, 0, s>>>(
           SX + row0 * d, row0, bx0, B, d, m, pl.kc, key, bscale, part);
     else
-      gsx_lowp_kernel<NB, FP8, false><<<grid, kThreads, 0, s>>>(SX + row0 * d, row0, bx0, B, d, m,
-                                                                pl.kc, key, bscale, part);
+      gsx_lowp_pc_kernel<NB, FP8, false><<<grid, 2 * kThreads, 0, s>>>(SX + row0 * d, row0, bx0, B,
+                                                                      d, m, pl.kc, key, bscale, part);
   }
 }
 
@@ -1049,7 +1224,9 @@ GsxPlan plan_gsx(int64_t m, int64_t B, int64_t d, Prec prec, int kc_request, siz
     // 64 columns each: fewer, longer chunks than that cost more in split
     // partials (written and reduced) than they gain in parallelism, and
     // longer ones leave CUs idle (measured at m = 64, d = 32 and 64)
-    const int64_t target = 2048;
+    // (the reduced-precision contraction: about 1024 consumer wavefronts,
+    // each with a producer wavefront beside it)
+    const int64_t target = prec == Prec::Native ? 2048 : 1024;
     const int64_t units = (int64_t)pl.mgroups * pl.ngroups;
     kc = (B * units + target - 1) / target;
     // ... unless 64-column chunks leave fewer than 1024 wavefronts (a
