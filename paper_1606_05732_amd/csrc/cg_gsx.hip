@@ -484,8 +484,8 @@ __global__ __launch_bounds__(kThreads) void fp8_block_scale_kernel(const float* 
 // operand format as soon as the step begins, so only one step of FP32
 // values is ever held (registers decide the occupancy here).
 //
-// The kernel is bound by the vector ALUs (Philox's 64-bit products and
-// Box-Muller's transcendentals), so the rest is kept lean:
+// The contraction is bound by the vector ALUs (Philox's 64-bit products
+// and Box-Muller's transcendentals), so the rest is kept lean:
 //  * VEC (NB = 2 or 4, d a multiple of 16 NB): lane p takes the NB
 //    consecutive columns n0 + NB p + nb, one 8- or 16-byte load per row;
 //  * rows are addressed by 32-bit element offsets from S X (the host
@@ -533,170 +533,20 @@ __device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
   return __builtin_bit_cast(uint32_t, v);
 }
 
-// One launch covers the parts bx0 + blockIdx.x; SX points at row row0 of
-// S X (the host splits the parts so that every row a launch reads lies
-// below row0 + 2^30 / d).
-template <int NB, bool FP8, bool VEC>
-__global__ __launch_bounds__(kThreads, FP8 ? 2 : 4) void gsx_lowp_kernel(const float* __restrict__ SX,
-                                                            int64_t row0, int64_t bx0, int64_t B,
-                                                            int d, int m, int kc, Key key,
-                                                            const float2* __restrict__ bscale,
-                                                            float* __restrict__ part) {
-  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  // columns per block: one FP8 scale; one decision whether masks are needed
-  constexpr int KBLK = FP8 ? 128 : 32;
-  __shared__ float red[3 * 16 * NB * 64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int p = lane & 15, kq = lane >> 4;
-  const int group = blockIdx.y;
-  const uint32_t q = (uint32_t)(16 * group + p);
-  const int n0 = blockIdx.z * NB * 16;
-  v4f acc[4][NB];
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0, 0, 0, 0};
-  // this lane's columns, each clamped onto d - 1 when past it (such
-  // columns are zeroed when packed; with VEC they do not occur)
-  bool cok[NB];
-  uint32_t ccol[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int col = VEC ? n0 + NB * p + nb : n0 + 16 * nb + p;
-    cok[nb] = col < d;
-    ccol[nb] = 4u * (uint32_t)min(col, d - 1);   // bytes
-  }
-
-  const int64_t bx = bx0 + blockIdx.x;
-  const int64_t kbeg = (bx * kWaves + wave) * kc;
-  const int64_t kend = min(kbeg + (int64_t)kc, B);
-  // byte offsets (4 row d) of this lane's rows, relative to row0: S X
-  // holds rows row0 .. row0 + 2^30 / d - 1 of this launch.  Loads clamp to
-  // the chunk's last row (to B - 1 for a wavefront past B, which then
-  // loads once and adds nothing; B - 1 >= row0, since every launch starts
-  // below B)
-  const uint32_t ud = 4u * (uint32_t)d;
-  const uint32_t last = (uint32_t)((kend > kbeg ? kend : B) - 1 - row0) * ud;
-  uint32_t off = (uint32_t)(kbeg + kq * 8 - row0) * ud;
-  float xn[8][NB];
-  lowp_load_rows<NB, VEC>(SX, off, ud, last, ccol, xn);
-  for (int64_t kb = kbeg; kb < kend; kb += KBLK) {
-    float xscale = 1.0f, yscale = 1.0f;
-    if constexpr (FP8) {
-      const float2 sc = bscale[kb >> 7];
-      xscale = sc.x;
-      yscale = sc.y;
-    }
-    // FP8 block products are rescaled before they join the accumulator;
-    // BF16 needs no scale and accumulates directly
-    v4f tmp[4][NB];
-    if constexpr (FP8) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) tmp[t][nb] = v4f{0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int sub = 0; sub < KBLK / 32; ++sub) {
-      const int64_t base = kb + sub * 32 + kq * 8;
-      // rows past the chunk (only in its last step) hold clamped reloads:
-      // zero them.  A zero S X value makes its products with G exactly
-      // zero, so the normals of those columns need no mask of their own
-      // (they are finite, drawn from counters past the chunk).
-      if (kb + sub * 32 + 32 > kend) {   // the same in the whole wavefront
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) xn[e][nb] = base + e < kend ? xn[e][nb] : 0.0f;
-      }
-      // this step's S X operand, packed from the values that arrived
-      uint32_t xw[NB][4];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-#pragma unroll
-        for (int e = 0; e < 8; e += 2) {
-          float x0 = xn[e][nb], x1 = xn[e + 1][nb];
-          if constexpr (!VEC) {
-            x0 = cok[nb] ? x0 : 0.0f;
-            x1 = cok[nb] ? x1 : 0.0f;
-          }
-          if constexpr (FP8) {
-            uint32_t& w = xw[nb][e >> 2];
-            w = (e & 2) ? (uint32_t)cvt_fp8<true>(x0 * xscale, x1 * xscale, (int)w)
-                        : (uint32_t)cvt_fp8<false>(x0 * xscale, x1 * xscale, 0);
-          } else {
-            xw[nb][e >> 1] = bf16_pair(x0, x1);
-          }
-        }
-      }
-      // the next step's rows (past the chunk: clamped reloads of its last row)
-      off += 32 * ud;
-      lowp_load_rows<NB, VEC>(SX, off, ud, last, ccol, xn);
-      // G's operand, two columns of B at a time
-      uint32_t gw[4][4];
-#pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        float z0[4], z1[4];
-        box_muller(gauss_block((uint32_t)(base + e), q, key.k0, key.k1), z0, FP8 ? 64.0f : 1.0f);
-        box_muller(gauss_block((uint32_t)(base + e + 1), q, key.k0, key.k1), z1, FP8 ? 64.0f : 1.0f);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if constexpr (FP8) {
-            // columns e, e + 1 go to byte pair (e / 2) % 2 of word e / 4
-            uint32_t& w = gw[t][e >> 2];
-            w = (e & 2) ? (uint32_t)cvt_fp8<true>(z0[t], z1[t], (int)w)
-                        : (uint32_t)cvt_fp8<false>(z0[t], z1[t], 0);
-          } else {
-            gw[t][e >> 1] = bf16_pair(z0[t], z1[t]);
-          }
-        }
-      }
-      if constexpr (FP8) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const long ga = (long)gw[t][0] | ((long)gw[t][1] << 32);
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const long xa = (long)xw[nb][0] | ((long)xw[nb][1] << 32);
-            tmp[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ga, xa, tmp[t][nb], 0, 0, 0);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const v8bf gb = __builtin_bit_cast(v8bf, u32x4{gw[t][0], gw[t][1], gw[t][2], gw[t][3]});
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const v8bf xb = __builtin_bit_cast(v8bf, u32x4{xw[nb][0], xw[nb][1], xw[nb][2], xw[nb][3]});
-            acc[t][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb, xb, acc[t][nb], 0, 0, 0);
-          }
-        }
-      }
-    }
-    if constexpr (FP8) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[t][nb] += tmp[t][nb] * yscale;
-    }
-  }
-  block_reduce_store<float, NB, v4f, VEC>(acc, red, wave, lane, group, n0, m, d,
-                                          part + (size_t)bx * m * d);
-}
-
-// Producer/consumer form of the reduced-precision contraction: eight
-// wavefronts per workgroup.  Wavefront c < 4 is a consumer with the chunk
-// of gsx_lowp_kernel's wavefront c: it loads and packs S X and multiplies.
-// Wavefront c + 4 is its producer: its lane l draws and packs, a 32-column
-// step ahead, exactly the G operand consumer lane l would draw (eight
-// Philox blocks, Box-Muller, BF16 pairs or FP8 bytes), into a double-
+// The reduced-precision contraction, in producer/consumer form: eight
+// wavefronts per workgroup.  Wavefront c < 4 is a consumer: it owns chunk
+// c of the workgroup's 4 kc columns of G, loads and packs S X (as above)
+// and multiplies.  Wavefront c + 4 is its producer: its lane l draws and
+// packs, a 32-column step ahead, the G operand of consumer lane l (eight
+// Philox blocks, Box-Muller, BF16 pairs or FP8 bytes) into a double-
 // buffered LDS slot of that lane.  The producers never wait on memory, so
-// the consumers' S X loads wait behind their work.  Same operands, same
-// MFMA order, same accumulation and cross-wavefront sum as
-// gsx_lowp_kernel: the partials are bit for bit its partials.  Every
+// the consumers' S X loads wait behind their work (one wavefront doing both
+// was slower at the planner's chunk size, 1024 consumer wavefronts).  Every
 // consumer runs all kc / 32 steps of its chunk (steps past its end, which
 // only the last chunk has, multiply zeroed S X), so that the eight
-// wavefronts meet at the same barriers.
+// wavefronts meet at the same barriers.  One launch covers the parts
+// bx0 + blockIdx.x; SX points at row row0 of S X (the host splits the parts
+// so that every row a launch reads lies below row0 + 2^30 / d).
 template <int NB, bool FP8, bool VEC>
 __global__ __launch_bounds__(2 * kThreads) void gsx_lowp_pc_kernel(
     const float* __restrict__ SX, int64_t row0, int64_t bx0, int64_t B, int d, int m, int kc,
