@@ -18,7 +18,8 @@ LIMIT = {"native": 1e-5, "bf16": 1e-2, "fp8": 5e-2}
 
 
 @pytest.mark.parametrize("n,d,m,B", [(20000, 64, 64, 4096), (9000, 17, 70, 1000),
-                                     (3000, 8, 5, 300), (5000, 100, 33, 640)])
+                                     (3000, 8, 5, 300), (5000, 100, 33, 640),
+                                     (4000, 40, 48, 800)])
 @pytest.mark.parametrize("prec", ["native", "bf16", "fp8"])
 def test_ladder_small(cuda, n, d, m, B, prec):
     rng = np.random.default_rng(n + d)

@@ -32,6 +32,7 @@ def _dense_case(n, d, seed, dtype):
 SHAPES = [
     (1, 1, 1, 1), (5, 3, 7, 2), (3000, 10, 20, 2000), (5000, 32, 64, 4096),
     (4099, 17, 65, 777), (2500, 64, 130, 5000), (1500, 65, 9, 300), (700, 300, 33, 1000),
+    (2000, 40, 64, 700),
 ]
 
 
